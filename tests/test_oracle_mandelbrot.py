@@ -1,0 +1,178 @@
+"""Pins of the oracle's escape-time Mandelbrot against what mathematics fixes.
+
+The paper computes "the Mandelbrot set" (Sec. 7.4, Sec. 7.5) without a
+formula; the oracle takes the textbook escape-time rule (z_0 = 0,
+z <- z^2 + c, count = first k with |z_k|^2 > 4, else max_iter).  None of
+these checks re-types the oracle's floating point loop: they use hand-derived
+orbits, exact rational arithmetic, symmetry, a classical asymptote and set
+geometry, so a dropped term, a wrong sign, a swapped coordinate, a ">=" for
+">" or an off-by-one count fails at least one of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_1505_07368_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+FPS = ("f32", "f64")
+
+
+# Orbits worked out by hand (z_0 = 0, z_1 = c, ...):
+#   c = 0:     0, 0, ...                     bounded            -> max_iter
+#   c = -1:    0, -1, 0, -1, ...             bounded            -> max_iter
+#   c = -2:    0, -2, 2, 2, ...  |z|^2 = 4 exactly, never > 4   -> max_iter
+#   c = 1/4:   0 < z_k < 1/2, increasing     bounded            -> max_iter
+#   c = i:     0, i, -1+i, -i, -1+i, ...     bounded            -> max_iter
+#   c = 1:     0, 1, 2, 5                    |z_3|^2 = 25 > 4   -> 3
+#   c = 2i:    0, 2i, -4+2i                  |z_1|^2 = 4 not > 4, |z_2|^2 = 20 -> 2
+#   c = 1/2:   0, .5, .75, 1.0625, 1.62890625, 3.1533...        -> 5
+#   c = -2.5:  |z_1|^2 = 6.25 > 4                               -> 1
+#   c = -2.5-1.25i: |z_1|^2 = 7.8125 > 4                        -> 1
+HAND_ORBITS = [
+    (0j, None), (-1 + 0j, None), (-2 + 0j, None), (0.25 + 0j, None), (1j, None), (-1j, None),
+    (1 + 0j, 3), (2j, 2), (-2j, 2), (0.5 + 0j, 5), (-2.5 + 0j, 1), (-2.5 - 1.25j, 1),
+]
+
+
+@pytest.mark.parametrize("fp", FPS)
+@pytest.mark.parametrize("c,expect", HAND_ORBITS)
+def test_hand_orbits(c, expect, fp):
+    mi = 1000
+    assert o.escape(c, mi, fp) == (mi if expect is None else expect)
+
+
+@pytest.mark.parametrize("fp", FPS)
+def test_max_iter_extremes(fp):
+    # max_iter = 1: only z_0 = 0 is tested, which never escapes -> every count is 1.
+    img = o.mandelbrot(-3.0, -3.0, 0.5, 0.5, 13, 0, 13, 1, fp)
+    assert (img == 1).all()
+    # The largest count a uint16 can carry.
+    assert o.escape(0j, 65535, fp) == 65535
+
+
+def exact_count(c: complex, max_iter: int) -> int:
+    """Escape count in exact rational arithmetic (the definition itself)."""
+    cr, ci = Fraction(c.real), Fraction(c.imag)
+    zr = zi = Fraction(0)
+    n = 0
+    while n < max_iter:
+        if zr * zr + zi * zi > 4:
+            break
+        zr, zi = zr * zr - zi * zi + cr, 2 * zr * zi + ci
+        n += 1
+    return n
+
+
+@pytest.mark.parametrize("fp,max_iter", [("f32", 4), ("f64", 5)])
+def test_exact_rational_grid(fp, max_iter):
+    """A 15x11 grid with step 1/4 from -2.5-1.25i: every c has two fractional
+    bits, so the tested iterates are exact in the given precision for this
+    many iterations and the floating-point counts must equal the exact
+    rational ones.  Pins the pixel -> c mapping (lower-left corner, global
+    row index, row-major layout) as well as the recurrence."""
+    W, H = 15, 11
+    img = o.mandelbrot(-2.5, -1.25, 0.25, 0.25, W, 0, H, max_iter, fp)
+    for y in range(H):
+        for x in range(W):
+            c = complex(-2.5 + 0.25 * x, -1.25 + 0.25 * y)
+            assert img[y, x] == exact_count(c, max_iter), (x, y, c)
+    # A tile that starts at row 7 samples the same global rows.
+    tile = o.mandelbrot(-2.5, -1.25, 0.25, 0.25, W, 7, 3, max_iter, fp)
+    assert (tile == img[7:10]).all()
+
+
+def test_non_square_pixels_and_asymmetric_axes():
+    """Distinct x and y steps: pixel (x, y) must use step_re for x and
+    step_im for y; the grid is not symmetric under x <-> y."""
+    W, H = 9, 5
+    img = o.mandelbrot(-2.0, -1.0, 0.5, 0.5 * 1.0, W, 0, H, 5, "f64")
+    img2 = o.mandelbrot(-2.0, -1.0, 0.5, 0.25, W, 0, H, 5, "f64")
+    for y in range(H):
+        for x in range(W):
+            assert img[y, x] == exact_count(complex(-2 + 0.5 * x, -1 + 0.5 * y), 5)
+            assert img2[y, x] == exact_count(complex(-2 + 0.5 * x, -1 + 0.25 * y), 5)
+
+
+@pytest.mark.parametrize("fp", FPS)
+def test_conjugate_symmetry_tiny(fp):
+    """Conjugation commutes with round-to-nearest arithmetic, and on the
+    512x512 grid every c is exact with row 256 on the real axis, so
+    out[y] == out[512 - y] bit for bit."""
+    vp = gen.tiny_viewport()
+    img = o.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 512, 0, 512, 100, fp)
+    for y in range(1, 512):
+        assert (img[y] == img[512 - y]).all(), y
+
+
+@pytest.mark.parametrize("fp,eps,tol", [("f32", 1e-2, 0.06), ("f32", 1e-4, 0.02),
+                                        ("f64", 1e-4, 0.02), ("f64", 1e-6, 0.02)])
+def test_parabolic_asymptote(fp, eps, tol):
+    """Near the cusp c = 1/4 + eps, the escape count n satisfies
+    n * sqrt(eps) -> pi as eps -> 0 (the parabolic-implosion estimate)."""
+    n = o.escape(complex(0.25 + eps, 0.0), 100000 if eps < 1e-5 else 10000, fp)
+    assert abs(n * math.sqrt(eps) - math.pi) / math.pi < tol, n
+
+
+@pytest.mark.parametrize("fp", FPS)
+def test_interior_and_exterior_geometry(fp):
+    """Points well inside the main cardioid or the period-2 bulb never
+    escape; points with |c| > 2 escape at the first test (count 1)."""
+    vp = gen.tiny_viewport()
+    mi = 100
+    img = o.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 512, 0, 512, mi, fp)
+    xs = vp.re_min + np.arange(512) * vp.step_re
+    ys = vp.im_min + np.arange(512) * vp.step_im
+    X, Y = np.meshgrid(xs, ys)
+    q = (X - 0.25) ** 2 + Y ** 2
+    cardioid = q * (q + (X - 0.25)) < 0.25 * Y ** 2 * 0.8  # 20 % margin
+    bulb = (X + 1) ** 2 + Y ** 2 < (1 / 16) * 0.8
+    outside = X ** 2 + Y ** 2 > 4.0 * 1.0001
+    assert cardioid.sum() > 1000 and bulb.sum() > 100 and outside.sum() > 1000
+    assert (img[cardioid] == mi).all()
+    assert (img[bulb] == mi).all()
+    assert (img[outside] == 1).all()
+
+
+@pytest.mark.parametrize("fp", FPS)
+def test_tiling_invariance(fp):
+    """64-row tiles with global row indices reproduce the whole image,
+    including the ragged last tile."""
+    vp = gen.boundary_viewport(3, width=96, height=150, max_iter=300)
+    whole = o.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 96, 0, 150, 300, fp)
+    parts = [o.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 96, r0, rows, 300, fp)
+             for r0, rows in gen.row_tiles(150, 64)]
+    assert [p.shape[0] for p in parts] == [64, 64, 22]
+    assert (np.concatenate(parts) == whole).all()
+
+
+def test_empty_tile():
+    assert o.mandelbrot(-2, -1, 0.1, 0.1, 7, 0, 0, 50).shape == (0, 7)
+
+
+def test_tiny_regression_figures():
+    """Sums computed independently of the oracle when the workloads were
+    surveyed (a separate scalar implementation)."""
+    with open(os.path.join(GOLDEN, "tiny_mandelbrot_summary.json")) as f:
+        ref = json.load(f)
+    vp = gen.tiny_viewport()
+    imgs = {}
+    for fp in FPS:
+        img = o.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 512, 0, 512, 100, fp)
+        imgs[fp] = img
+        assert int(img.sum(dtype=np.int64)) == ref[fp]["sum"]
+        assert int((img == 100).sum()) == ref[fp]["at_max_iter"]
+    assert int((imgs["f32"] != imgs["f64"]).sum()) == ref["f32_vs_f64_differing_pixels"]
+
+
+def test_precisions_differ_near_cusp():
+    """Float and double counts are each exact for their own arithmetic and
+    need not agree: near c = 1/4 they differ (3119 vs 3140 iterations)."""
+    a = o.escape(complex(0.25 + 1e-6, 0), 100000, "f32")
+    b = o.escape(complex(0.25 + 1e-6, 0), 100000, "f64")
+    assert a != b
