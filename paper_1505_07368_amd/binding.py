@@ -1,0 +1,365 @@
+"""ctypes binding of libcafgpu.so (include/caf_gpu.h), plus a thin wrapper.
+
+The functions named caf_* are the C ABI itself, with the same names and
+arguments.  ``System``/``Future`` only marshal arguments: PyTorch provides
+the device memory (the arena tensor, input and output tensors) and the
+streams; every step of a message runs in the library's HIP kernels.  If the
+library is missing this module raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcafgpu.so")
+
+OK, E_INVALID, E_NO_ACTOR, E_OVERLOAD, E_TIMEOUT, E_DEVICE, E_QUIT, E_FAULT = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+I32, U16, F32, F64, BF16, U64 = 0, 1, 2, 3, 4, 5
+BHV_NOOP, BHV_MANDELBROT, BHV_GEMM, BHV_TANH, BHV_ROWSUM, BHV_HASHCHAIN, BHV_FAULT = range(7)
+MODE_PLAIN, MODE_BATCHED, MODE_PERSISTENT = 0, 1, 2
+GROUP_FIFO, GROUP_LPT = 0, 1
+MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "persistent": MODE_PERSISTENT}
+
+EXPORTED = ["caf_gpu_init", "caf_gpu_spawn", "caf_gpu_send", "caf_gpu_request",
+            "caf_future_wait", "caf_future_poll", "caf_future_id", "caf_future_release",
+            "caf_gpu_quit", "caf_gpu_drain", "caf_gpu_shutdown", "caf_gpu_strerror",
+            "caf_gpu_get_stats", "caf_gpu_drain_kernel_ms", "caf_gpu_drive"]
+
+
+class caf_buf(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("numel", C.c_uint64), ("dtype", C.c_int32),
+                ("on_device", C.c_uint32)]
+
+
+class caf_gpu_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("mode", C.c_int32), ("stream", C.c_void_p),
+                ("drain_stream", C.c_void_p), ("arena", C.c_void_p),
+                ("arena_bytes", C.c_uint64), ("ring_slots", C.c_uint32),
+                ("max_batch", C.c_uint32), ("grid", C.c_uint32), ("blocking", C.c_uint32),
+                ("idle_exit_us", C.c_uint32), ("grouping", C.c_int32),
+                ("mandel_tile_px", C.c_uint32), ("gemm_tile", C.c_uint32)]
+
+
+class caf_mandel_args(C.Structure):
+    _fields_ = [("re_min", C.c_double), ("im_min", C.c_double), ("step_re", C.c_double),
+                ("step_im", C.c_double), ("width", C.c_uint32), ("height", C.c_uint32),
+                ("row0", C.c_uint32), ("rows", C.c_uint32), ("max_iter", C.c_uint32),
+                ("fp", C.c_int32)]
+
+
+class caf_gemm_args(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("in_dtype", C.c_int32)]
+
+
+class caf_shape_args(C.Structure):
+    _fields_ = [("rows", C.c_uint32), ("cols", C.c_uint32)]
+
+
+class caf_hash_args(C.Structure):
+    _fields_ = [("x", C.c_uint64)]
+
+
+class caf_spawn_args(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("reserved", C.c_uint32), ("forward_to", C.c_uint64)]
+
+
+class caf_gpu_stats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in (
+        "requests", "sends", "completions", "launches", "drain_launches",
+        "duplicate_completions", "swallowed", "arena_in_use", "arena_peak", "rejected",
+        "device_drained", "outstanding")]
+
+
+class caf_msg(C.Structure):
+    _fields_ = [("actor", C.c_uint64), ("sender", C.c_uint32), ("n_in", C.c_uint32),
+                ("args", C.c_void_p), ("args_bytes", C.c_uint64), ("in_", C.c_void_p),
+                ("out", caf_buf), ("forward_to", C.c_uint64)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libcafgpu.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, i32, i64 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_int64
+    P = C.POINTER
+    sig = {
+        "caf_gpu_init": ([P(caf_gpu_config), P(vp)], C.c_int),
+        "caf_gpu_spawn": ([vp, i32, P(caf_spawn_args), P(u64)], C.c_int),
+        "caf_gpu_send": ([vp, u64, u32, vp, u64, P(caf_buf), u32], C.c_int),
+        "caf_gpu_request": ([vp, u64, u32, vp, u64, P(caf_buf), u32, P(caf_buf), u64, P(vp)],
+                            C.c_int),
+        "caf_future_wait": ([vp, i64, P(caf_buf), P(i32)], C.c_int),
+        "caf_future_poll": ([vp, P(caf_buf), P(i32)], C.c_int),
+        "caf_future_id": ([vp], u64),
+        "caf_future_release": ([vp], None),
+        "caf_gpu_quit": ([vp, u64, u32], C.c_int),
+        "caf_gpu_drain": ([vp, i64], C.c_int),
+        "caf_gpu_shutdown": ([vp], C.c_int),
+        "caf_gpu_strerror": ([C.c_int], C.c_char_p),
+        "caf_gpu_get_stats": ([vp, P(caf_gpu_stats)], C.c_int),
+        "caf_gpu_drain_kernel_ms": ([vp, P(u64)], C.c_double),
+        "caf_gpu_drive": ([vp, P(caf_msg), u64, u32, vp, u32, vp, vp, vp, P(C.c_double)],
+                          C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def strerror(st: int) -> str:
+    return load().caf_gpu_strerror(st).decode()
+
+
+class CafError(RuntimeError):
+    def __init__(self, what, st):
+        super().__init__(f"{what}: {strerror(st)} ({st})")
+        self.status = st
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t) -> int:
+    torch = _torch()
+    m = {torch.int32: I32, torch.uint16: U16, torch.float32: F32, torch.float64: F64,
+         torch.bfloat16: BF16, torch.uint64: U64}
+    return m[t.dtype]
+
+
+def buf_of(x, dtype: int | None = None) -> caf_buf:
+    """caf_buf for a torch tensor (device or host) or a numpy array (host)."""
+    if isinstance(x, np.ndarray):
+        assert x.flags.c_contiguous
+        np_map = {np.dtype(np.int32): I32, np.dtype(np.uint16): U16, np.dtype(np.float32): F32,
+                  np.dtype(np.float64): F64, np.dtype(np.uint64): U64}
+        return caf_buf(x.ctypes.data, x.size, dtype if dtype is not None else np_map[x.dtype], 0)
+    assert x.is_contiguous()
+    return caf_buf(x.data_ptr(), x.numel(), dtype if dtype is not None else dtype_code(x),
+                   1 if x.is_cuda else 0)
+
+
+_ELEM = {I32: 4, U16: 2, F32: 4, F64: 8, BF16: 2, U64: 8}
+
+
+class Future:
+    """A request's reply (exactly one)."""
+
+    def __init__(self, system: "System", handle: int, keep):
+        self.system = system
+        self.h = C.c_void_p(handle)
+        self._keep = keep  # inputs must outlive the request
+
+    @property
+    def id(self) -> int:
+        return int(load().caf_future_id(self.h))
+
+    def wait(self, timeout_s: float | None = None):
+        """Returns (reply_status, caf_buf); raises CafError on a timeout."""
+        res = caf_buf()
+        st = C.c_int32(0)
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        rc = load().caf_future_wait(self.h, t, C.byref(res), C.byref(st))
+        if rc == E_TIMEOUT:
+            raise CafError("wait", rc)
+        return st.value, res
+
+    def poll(self):
+        res = caf_buf()
+        st = C.c_int32(0)
+        r = load().caf_future_poll(self.h, C.byref(res), C.byref(st))
+        return (r == 1), st.value, res
+
+    def result(self, timeout_s: float | None = 60.0):
+        """Waits and returns (status, value): a torch tensor view of the
+        reply in the arena (device), a numpy array for inline replies, or
+        None for an error reply."""
+        st, res = self.wait(timeout_s)
+        if st != OK:
+            return st, None
+        return st, self.system.view(res)
+
+    def release(self):
+        if self.h:
+            load().caf_future_release(self.h)
+            self.h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class System:
+    """A compute-actor system on one GPU with a torch-allocated arena."""
+
+    def __init__(self, mode="persistent", arena_bytes=1 << 30, device=0, ring_slots=4096,
+                 max_batch=1024, grid=0, blocking=True, idle_exit_us=0, grouping="lpt",
+                 mandel_tile_px=0, gemm_tile=0):
+        torch = _torch()
+        self.L = load()
+        self.device = device
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self.stream = torch.cuda.Stream(device=device)
+        self.dstream = torch.cuda.Stream(device=device)
+        self.mode = MODES[mode] if isinstance(mode, str) else mode
+        cfg = caf_gpu_config(
+            device, self.mode, C.c_void_p(self.stream.cuda_stream),
+            C.c_void_p(self.dstream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
+            arena_bytes, ring_slots, max_batch, grid, 1 if blocking else 0, idle_exit_us,
+            GROUP_LPT if grouping == "lpt" else GROUP_FIFO, mandel_tile_px, gemm_tile)
+        torch.cuda.synchronize(device)
+        h = C.c_void_p()
+        rc = self.L.caf_gpu_init(C.byref(cfg), C.byref(h))
+        if rc != OK:
+            raise CafError("caf_gpu_init", rc)
+        self.h = h
+
+    # -- actors ----------------------------------------------------------
+    def spawn(self, behavior: int, n: int = 0, forward_to: int = 0) -> int:
+        a = C.c_uint64()
+        sa = caf_spawn_args(n, 0, forward_to)
+        rc = self.L.caf_gpu_spawn(self.h, behavior, C.byref(sa), C.byref(a))
+        if rc != OK:
+            raise CafError("caf_gpu_spawn", rc)
+        return a.value
+
+    def quit(self, actor: int, reason: int = 0) -> int:
+        return self.L.caf_gpu_quit(self.h, actor, reason)
+
+    @staticmethod
+    def _bufs(inputs):
+        bufs = (caf_buf * max(1, len(inputs)))()
+        for i, x in enumerate(inputs):
+            if isinstance(x, caf_buf):
+                bufs[i] = x
+            elif isinstance(x, tuple):
+                bufs[i] = buf_of(x[0], x[1])
+            else:
+                bufs[i] = buf_of(x)
+        return bufs
+
+    def request_raw(self, actor, args=None, inputs=(), out=None, forward_to=0, sender=0):
+        """Returns (status, Future or None)."""
+        ab = bytes(args) if args is not None else b""
+        bufs = self._bufs(inputs)
+        ob = buf_of(out) if out is not None else None
+        fut = C.c_void_p()
+        rc = self.L.caf_gpu_request(self.h, actor, sender, ab, len(ab), bufs, len(inputs),
+                                    C.byref(ob) if ob is not None else None, forward_to,
+                                    C.byref(fut))
+        if rc != OK:
+            return rc, None
+        return rc, Future(self, fut.value, (inputs, out, ab))
+
+    def request(self, actor, args=None, inputs=(), out=None, forward_to=0, sender=0) -> Future:
+        rc, f = self.request_raw(actor, args, inputs, out, forward_to, sender)
+        if rc != OK:
+            raise CafError("caf_gpu_request", rc)
+        return f
+
+    def send(self, actor, args=None, inputs=(), sender=0) -> int:
+        ab = bytes(args) if args is not None else b""
+        bufs = self._bufs(inputs)
+        return self.L.caf_gpu_send(self.h, actor, sender, ab, len(ab), bufs, len(inputs))
+
+    def drain(self, timeout_s: float = 60.0) -> int:
+        return self.L.caf_gpu_drain(self.h, int(timeout_s * 1e9))
+
+    def stats(self) -> dict:
+        s = caf_gpu_stats()
+        self.L.caf_gpu_get_stats(self.h, C.byref(s))
+        return {f: getattr(s, f) for f, _ in caf_gpu_stats._fields_}
+
+    def drain_kernel_ms(self):
+        n = C.c_uint64()
+        ms = self.L.caf_gpu_drain_kernel_ms(self.h, C.byref(n))
+        return ms, n.value
+
+    def view(self, res: caf_buf):
+        """The reply buffer as a tensor (device, a view into the arena or the
+        caller's out tensor) or a numpy array (inline host reply)."""
+        torch = _torch()
+        if res.numel == 0:
+            return None
+        if not res.on_device:
+            nb = res.numel * _ELEM[res.dtype]
+            raw = (C.c_uint8 * nb).from_address(res.data)
+            npd = {I32: np.int32, U16: np.uint16, F32: np.float32, F64: np.float64,
+                   U64: np.uint64}[res.dtype]
+            return np.frombuffer(bytes(raw), dtype=npd).copy()
+        off = res.data - self.arena.data_ptr()
+        nb = res.numel * _ELEM[res.dtype]
+        if 0 <= off and off + nb <= self.arena.numel():
+            tdt = {I32: torch.int32, U16: torch.uint16, F32: torch.float32,
+                   F64: torch.float64, U64: torch.uint64}[res.dtype]
+            return self.arena[off:off + nb].view(tdt)
+        return None  # written into a caller-owned out tensor
+
+    def drive(self, msgs, window=1, arrival_ns=None, chain_hops=0, hop_actors=()):
+        """Runs caf_gpu_drive; msgs: list of dicts with actor, args, inputs,
+        out, forward_to, sender.  Returns (rc, latency_ns, status, elapsed_s)."""
+        n = len(msgs)
+        arr = (caf_msg * max(1, n))()
+        keep = []
+        for i, m in enumerate(msgs):
+            ab = bytes(m["args"]) if m.get("args") is not None else b""
+            abuf = C.create_string_buffer(ab, max(1, len(ab)))
+            ins = m.get("inputs", ())
+            bufs = self._bufs(ins)
+            keep.append((abuf, bufs, ins, m.get("out")))
+            out = buf_of(m["out"]) if m.get("out") is not None else caf_buf()
+            arr[i] = caf_msg(m["actor"], m.get("sender", 0), len(ins), C.addressof(abuf),
+                             len(ab), C.addressof(bufs), out, m.get("forward_to", 0))
+        lat = np.full(n, -1, np.int64)
+        st = np.full(n, E_INVALID, np.int32)
+        arrival = None
+        if arrival_ns is not None:
+            arrival = np.ascontiguousarray(arrival_ns, np.int64)
+        hops = (C.c_uint64 * max(1, len(hop_actors)))(*hop_actors)
+        el = C.c_double()
+        rc = self.L.caf_gpu_drive(self.h, arr, n, window,
+                                  arrival.ctypes.data if arrival is not None else None,
+                                  chain_hops, hops, lat.ctypes.data, st.ctypes.data,
+                                  C.byref(el))
+        return rc, lat, st, el.value
+
+    def shutdown(self):
+        if getattr(self, "h", None):
+            self.L.caf_gpu_shutdown(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.shutdown()
+
+    def __del__(self):
+        try:
+            self.shutdown()
+        except Exception:
+            pass
+
+
+def mandel_args(vp, row0=0, rows=None, fp=F32, max_iter=None) -> caf_mandel_args:
+    rows = vp.height - row0 if rows is None else rows
+    return caf_mandel_args(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, vp.height,
+                           row0, rows, vp.max_iter if max_iter is None else max_iter, fp)

@@ -1,0 +1,182 @@
+// Internal layouts of the compute-actor library: the mailbox entry
+// (descriptor), the completion record, the control blocks shared between
+// the host runtime and the drain kernel, and the work-tile geometry.  Used
+// by the host runtime and the device code of this library only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/caf_gpu.h"
+
+namespace cafgpu {
+
+constexpr uint32_t kMaxActors = 1024;
+constexpr uint32_t kAliveWords = kMaxActors / 32;
+constexpr uint32_t kThreads = 256;  // one workgroup = 4 wave64s
+constexpr uint32_t kInlineBytes = 16;
+constexpr uint32_t kMaxHops = 2;
+constexpr uint32_t kMaxBatch = 1024;
+constexpr uint32_t kSlotBits = 20;  // request id = (sequence << kSlotBits) | slot
+constexpr uint32_t kMaxSlots = 1u << kSlotBits;
+constexpr uint32_t kTanhTile = 4096;   // elements per tanh work tile
+constexpr uint32_t kRowsumTile = 16;   // rows per row-sum work tile
+constexpr uint32_t kMandelBlockW = 16; // a wave's pixel block: 4 rows x 16 columns
+constexpr uint32_t kMandelBlockH = 4;
+
+enum DescFlags : uint16_t {
+  DF_FP64 = 1,       // Mandelbrot in double (else float)
+  DF_BF16 = 2,       // GEMM inputs are bfloat16 (else float)
+  DF_INLINE_IN = 4,  // echo input travels in the parameter block
+  DF_INLINE_OUT = 8, // reply (<= 16 B) travels in the completion record
+  DF_SEND = 16,      // no reply wanted; the completion only recycles the slot
+  DF_NO_COMPLETE = 32 // plain mode, non-final pipeline stage: no completion record
+};
+
+// One message: a 128-byte mailbox entry.
+struct alignas(16) Desc {
+  uint64_t req_id;     // 0
+  uint32_t slot;       // 8: index of the request's device slot
+  uint32_t actor;      // 12: actor index
+  uint16_t behavior;   // 16
+  uint16_t flags;      // 18
+  uint32_t seq;        // 20: per-actor sequence number (stateful ordering)
+  uint64_t in0;        // 24: device pointers of the inputs ...
+  uint64_t in1;        // 32
+  uint64_t out;        // 40: ... and of the reply (the kernel's last parameter)
+  uint32_t hop_actor[kMaxHops];  // 48: forwarding chain, actor index + 1 (0 = none)
+  uint64_t hop_out[kMaxHops];    // 56: reply buffers of the hops
+  uint32_t tcfg;       // 72: work-tile size (GEMM tile edge / Mandelbrot px per tile)
+  uint32_t numel;      // 76: echo element count
+  union {              // 80: parameter block, 48 bytes
+    struct {
+      double re_min, im_min, step_re, step_im;
+      uint32_t width, row0, rows, max_iter;
+    } m64;
+    struct {
+      float re_min, im_min, step_re, step_im;
+      uint32_t pad[4];
+      uint32_t width, row0, rows, max_iter;
+    } m32;
+    struct { uint32_t n; } g;
+    struct { uint32_t rows, cols; } s;
+    struct { uint64_t x; } h;
+    uint8_t raw[48];
+  } p;
+};
+static_assert(sizeof(Desc) == 128, "descriptor is one 128-byte mailbox entry");
+
+// One reply notification, written by the device into host memory.
+struct alignas(32) Comp {
+  uint64_t req_id;
+  int32_t status;
+  uint32_t lap;  // written last (release): position / capacity + 1
+  uint8_t data[kInlineBytes];
+};
+static_assert(sizeof(Comp) == 32, "completion record is 32 bytes");
+
+// Host-resident (pinned, coherent) control block.
+struct alignas(64) HostCtl {
+  uint64_t tail;      // mailbox entries published by the host
+  uint8_t pad0[56];
+  uint64_t drained;   // mailbox entries copied to the device (device writes)
+  uint8_t pad1[56];
+  uint32_t stop;      // host asks the drain kernel to exit
+  uint32_t exited_gen;  // generation of the last drain launch that fully exited
+  uint8_t pad2[56];
+  uint32_t alive[kAliveWords];  // bit per actor
+};
+
+// Device-resident control block (agent-scope atomics only).
+struct alignas(64) DevCtl {
+  uint64_t drained;
+  uint8_t p0[56];
+  uint64_t tiles_pub;      // work tiles published (claimable below this)
+  uint8_t p1[56];
+  uint64_t tiles_claimed;  // claim cursor
+  uint8_t p2[56];
+  uint64_t tiles_done;
+  uint8_t p3[56];
+  uint32_t drain_lock;
+  uint8_t p4[60];
+  uint32_t wg_exited;
+  uint8_t p5[60];
+  uint64_t comp_tail;      // completion positions handed out
+  uint8_t p6[56];
+  uint32_t stop_seen;      // a drainer saw the host's stop flag
+  uint8_t p7[60];
+};
+
+struct alignas(16) DevSlot {
+  Desc d;              // the message currently held by this slot
+  uint64_t tile_base;  // first global tile index of the message
+  uint32_t ntiles;
+  uint32_t pad;
+  uint8_t inline_out[kInlineBytes];
+};
+
+struct alignas(16) SlotState {
+  uint32_t done;      // tiles finished of the current stage
+  uint32_t decision;  // plain mode: 0 undecided, 1 run, 2 actor quit
+  int32_t status;     // reply status carried along a pipeline
+  uint32_t pad;
+};
+
+struct alignas(16) DevActor {
+  uint64_t state;     // hash-chain state (device-resident actor state)
+  uint32_t seq_done;  // messages of this actor handled so far
+  uint32_t pad;
+};
+
+// Everything a kernel needs, passed by value.
+struct KArgs {
+  HostCtl* hctl;
+  Desc* hring;
+  Comp* comp;
+  DevCtl* dctl;
+  DevSlot* slots;
+  SlotState* sstate;
+  uint32_t* tile2slot;
+  DevActor* actors;
+  uint32_t cap, ccap, tcap, max_batch;
+  uint64_t idle_ticks;    // persistent: exit after this many wall-clock ticks idle
+  uint64_t wait_ticks;    // bound of any device-side wait
+  uint32_t gen;           // launch generation
+  uint32_t exit_on_empty; // batched mode
+  uint32_t grouping;
+  uint32_t grid;
+};
+
+// ---- work-tile geometry (host and device agree on it) -------------------
+
+__host__ __device__ inline uint32_t mandel_blocks(uint32_t width, uint32_t rows) {
+  uint32_t bw = (width + kMandelBlockW - 1) / kMandelBlockW;
+  uint32_t bh = (rows + kMandelBlockH - 1) / kMandelBlockH;
+  return bw * bh;
+}
+
+__host__ __device__ inline uint32_t desc_ntiles(const Desc& d) {
+  switch (d.behavior) {
+    case CAF_BHV_MANDELBROT: {
+      uint32_t w = d.p.m64.width, r = d.p.m64.rows;  // same offsets in m32
+      uint32_t bpt = d.tcfg / 64;
+      uint32_t nb = mandel_blocks(w, r);
+      return nb == 0 ? 1u : (nb + bpt - 1) / bpt;  // an empty tile still replies
+    }
+    case CAF_BHV_GEMM: {
+      uint32_t te = d.tcfg;
+      uint32_t t = (d.p.g.n + te - 1) / te;
+      return t * t;
+    }
+    case CAF_BHV_TANH: {
+      uint64_t ne = (uint64_t)d.p.s.rows * d.p.s.cols;
+      return (uint32_t)((ne + kTanhTile - 1) / kTanhTile);
+    }
+    case CAF_BHV_ROWSUM:
+      return (d.p.s.rows + kRowsumTile - 1) / kRowsumTile;
+    default:
+      return 1;
+  }
+}
+
+}  // namespace cafgpu

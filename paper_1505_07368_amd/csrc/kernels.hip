@@ -1,0 +1,617 @@
+// Device side of the compute actor (gfx950).
+//
+// Two kernels share the work-tile functions of tiles.h and one completion
+// protocol:
+//
+//  * plain_kernel -- one launch per message (the baseline form): the
+//    message's descriptor travels as a kernel argument, one workgroup per
+//    work tile.
+//
+//  * drain_kernel -- the mailbox drain.  Messages sit in a host-written
+//    mailbox ring (pinned, coherent host memory).  A workgroup that finds
+//    no claimable work takes the drain lock, reads the ring tail, copies up
+//    to max_batch entries (the paper's max_msgs per scheduling slot, Sec. 6)
+//    into device-resident slots, checks each actor is alive, groups the
+//    batch (by behaviour, largest GEMMs first, or mailbox order), prefix-sums
+//    the per-message work-tile counts into one global tile sequence and
+//    publishes it.  Every workgroup claims tiles of that sequence one at a
+//    time with a compare-and-swap bounded by the published count, so no
+//    workgroup ever waits for one that may not be resident.  The
+//    workgroup finishing a message's last tile either publishes its reply
+//    (a completion record in host memory, released at system scope) or
+//    forwards the reply to the next actor of a pipeline as a new message
+//    on the device (no host round trip).
+//
+//    Batched mode: the kernel exits once the ring is empty and no work is
+//    claimable.  Persistent mode: it stays resident, backing off while
+//    idle, and exits at the stop flag or after idle_ticks without work.
+//    Every device-side wait is bounded by wait_ticks of the wall clock.
+//
+// Requests are FIFO per (sender, actor) because the host appends to the
+// ring in call order and the drain preserves each actor's relative order;
+// stateful actors (the hash chain) additionally wait for their previous
+// message's sequence number before updating device-resident state.
+#pragma clang fp contract(off)
+
+#include "caf_internal.h"
+#include "tiles.h"
+
+namespace cafgpu {
+
+// ---- scoped memory operations ---------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T ld_sys(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ T ld_sys_acq(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ void st_sys(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ void st_sys_rel(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_dev_acq(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev_rel(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ bool cas_dev(T* p, T& expected, T desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t now_ticks() { return wall_clock64(); }
+
+__device__ __forceinline__ void backoff_sleep(uint32_t rounds) {
+  for (uint32_t i = 0; i < rounds; ++i) __builtin_amdgcn_s_sleep(32);
+}
+
+__device__ __forceinline__ bool actor_alive(const HostCtl* h, uint32_t actor) {
+  return (ld_sys(&h->alive[actor >> 5]) >> (actor & 31)) & 1u;
+}
+
+// ---- completion -------------------------------------------------------------
+
+// Publishes one reply notification to the host (thread-level).
+__device__ void write_completion(const KArgs& a, uint64_t req_id, int32_t status,
+                                 const uint8_t* data) {
+  const uint64_t pos = __hip_atomic_fetch_add(&a.dctl->comp_tail, (uint64_t)1,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  Comp* c = &a.comp[pos % a.ccap];
+  st_sys(&c->req_id, req_id);
+  st_sys(&c->status, status);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(c->data);
+  for (int i = 0; i < 4; ++i) {
+    uint32_t v = 0;
+    if (data) v = reinterpret_cast<const uint32_t*>(data)[i];
+    st_sys(dst + i, v);
+  }
+  st_sys_rel(&c->lap, (uint32_t)(pos / a.ccap) + 1u);
+}
+
+// Appends `nt` tiles of slot `slot` to the global tile sequence (caller
+// holds the drain lock).  Returns false if the tile map has no room within
+// the wait bound.
+__device__ bool publish_tiles_locked(const KArgs& a, uint32_t slot, uint32_t nt) {
+  uint64_t t0 = now_ticks();
+  uint64_t pub = ld_dev_acq(&a.dctl->tiles_pub);
+  while (pub + nt > ld_dev_acq(&a.dctl->tiles_done) + a.tcap / 2) {
+    if (now_ticks() - t0 > a.wait_ticks) return false;
+    backoff_sleep(2);
+  }
+  a.slots[slot].tile_base = pub;
+  a.slots[slot].ntiles = nt;
+  for (uint32_t t = 0; t < nt; ++t) a.tile2slot[(pub + t) % a.tcap] = slot;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  st_dev_rel(&a.dctl->tiles_pub, pub + nt);
+  return true;
+}
+
+__device__ bool lock_drain(const KArgs& a, bool bounded) {
+  uint64_t t0 = now_ticks();
+  for (;;) {
+    uint32_t z = 0;
+    if (ld_dev(&a.dctl->drain_lock) == 0 && cas_dev(&a.dctl->drain_lock, z, 1u)) return true;
+    if (!bounded) return false;
+    if (now_ticks() - t0 > a.wait_ticks) return false;
+    backoff_sleep(1);
+  }
+}
+
+__device__ void unlock_drain(const KArgs& a) { st_dev_rel(&a.dctl->drain_lock, 0u); }
+
+// Forwards the finished reply of `d` to the next actor of its pipeline as a
+// new message in the same slot (thread-level, drain kernel only).
+__device__ __noinline__ void forward_reply(const KArgs& a, const Desc& d) {
+  const uint32_t slot = d.slot;
+  const uint32_t hop = d.hop_actor[0];
+  const uint32_t actor = (hop & 0xFFFFu) - 1u;
+  const uint16_t behavior = (uint16_t)(hop >> 16);
+  if (!actor_alive(a.hctl, actor)) {
+    write_completion(a, d.req_id, CAF_E_QUIT, nullptr);
+    return;
+  }
+  Desc nd = d;
+  nd.actor = actor;
+  nd.behavior = behavior;
+  nd.in0 = d.out;
+  nd.in1 = 0;
+  nd.out = d.hop_out[0];
+  nd.hop_actor[0] = d.hop_actor[1];
+  nd.hop_out[0] = d.hop_out[1];
+  nd.hop_actor[1] = 0;
+  nd.hop_out[1] = 0;
+  const uint32_t rows = d.behavior == CAF_BHV_GEMM ? d.p.g.n : d.p.s.rows;
+  const uint32_t cols = d.behavior == CAF_BHV_GEMM ? d.p.g.n : d.p.s.cols;
+  for (int i = 0; i < 48; ++i) nd.p.raw[i] = 0;
+  nd.p.s.rows = rows;
+  nd.p.s.cols = cols;
+  nd.flags = (uint16_t)(d.flags & DF_SEND);
+  nd.tcfg = 0;
+  a.slots[slot].d = nd;
+  const uint32_t nt = desc_ntiles(nd);
+  bool ok = lock_drain(a, true);
+  if (ok) {
+    ok = publish_tiles_locked(a, slot, nt);
+    unlock_drain(a);
+  }
+  if (!ok) write_completion(a, d.req_id, CAF_E_DEVICE, nullptr);
+}
+
+// Accounts one finished tile of message `d` (thread 0, after the
+// workgroup's tile work is complete).  The last tile of a message resets
+// the slot's counters and completes or forwards it.
+__device__ void finish_tile(const KArgs& a, const Desc& d, uint32_t ntiles, bool ring) {
+  const uint32_t slot = d.slot;
+  SlotState* ss = &a.sstate[slot];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  const uint32_t prev = __hip_atomic_fetch_add(&ss->done, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+  if (prev + 1 == ntiles) {
+    const int32_t st = ld_dev(&ss->status);
+    st_dev(&ss->done, 0u);
+    st_dev(&ss->decision, 0u);
+    if (ring && st == CAF_OK && d.hop_actor[0] != 0) {
+      forward_reply(a, d);
+    } else if (!(d.flags & DF_NO_COMPLETE)) {
+      st_dev(&ss->status, 0);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint8_t* data = (d.flags & DF_INLINE_OUT) ? a.slots[slot].inline_out : nullptr;
+      write_completion(a, d.req_id, st, data);
+    }
+  }
+  if (ring) __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- behaviour dispatch -----------------------------------------------------
+
+__device__ void hash_step(const KArgs& a, const Desc& d) {
+  if (threadIdx.x != 0) return;
+  DevActor* act = &a.actors[d.actor];
+  const uint64_t t0 = now_ticks();
+  while (ld_dev_acq(&act->seq_done) != d.seq) {
+    if (now_ticks() - t0 > a.wait_ticks) {
+      st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_DEVICE);
+      return;
+    }
+    backoff_sleep(1);
+  }
+  const uint64_t s = (ld_dev(&act->state) * 1000003ull) ^ d.p.h.x;
+  st_dev(&act->state, s);
+  uint64_t* io = reinterpret_cast<uint64_t*>(a.slots[d.slot].inline_out);
+  io[0] = s;
+  io[1] = 0;
+  st_dev_rel(&act->seq_done, d.seq + 1u);
+}
+
+__device__ void run_tile(const KArgs& a, const Desc& d, uint32_t tile, uint8_t* smem,
+                         uint32_t* lds_ctr) {
+  switch (d.behavior) {
+    case CAF_BHV_MANDELBROT:
+      if (d.flags & DF_FP64) mandel_tile<double>(d, tile, lds_ctr);
+      else mandel_tile<float>(d, tile, lds_ctr);
+      break;
+    case CAF_BHV_GEMM: {
+      float* C = reinterpret_cast<float*>(d.out);
+      if (d.flags & DF_BF16) {
+        const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
+        const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
+        if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
+        else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
+      } else {
+        const float* A = reinterpret_cast<const float*>(d.in0);
+        const float* B = reinterpret_cast<const float*>(d.in1);
+        if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, (float*)smem);
+        else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, (float*)smem);
+      }
+      break;
+    }
+    case CAF_BHV_TANH:
+      tanh_tile(reinterpret_cast<const float*>(d.in0), reinterpret_cast<float*>(d.out),
+                (uint64_t)d.p.s.rows * d.p.s.cols, tile);
+      break;
+    case CAF_BHV_ROWSUM:
+      rowsum_tile(reinterpret_cast<const float*>(d.in0), reinterpret_cast<float*>(d.out),
+                  d.p.s.rows, d.p.s.cols, tile);
+      break;
+    case CAF_BHV_NOOP:
+      echo_tile(d, a.slots[d.slot].inline_out);
+      break;
+    case CAF_BHV_HASHCHAIN:
+      hash_step(a, d);
+      break;
+    case CAF_BHV_FAULT:
+      if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_FAULT);
+      break;
+    default:
+      if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_INVALID);
+      break;
+  }
+}
+
+constexpr uint32_t kSmemBytes = 2 * 128 * 40 * 2;  // largest tile: bf16 GEMM, TE = 128
+
+// ---- one launch per message -------------------------------------------------
+
+__global__ void __launch_bounds__(kThreads) plain_kernel(KArgs a, Desc d, uint32_t ntiles) {
+  __shared__ __align__(16) uint8_t smem[kSmemBytes];
+  __shared__ uint32_t s_dec;
+  __shared__ uint32_t s_ctr;
+  const uint32_t slot = d.slot;
+  SlotState* ss = &a.sstate[slot];
+  if (threadIdx.x == 0) {
+    // All workgroups of the message agree on one reading of the actor's
+    // alive flag: the first to arrive decides.
+    uint32_t dec = ld_dev_acq(&ss->decision);
+    if (dec == 0) {
+      const uint32_t v = actor_alive(a.hctl, d.actor) ? 1u : 2u;
+      uint32_t z = 0;
+      dec = cas_dev(&ss->decision, z, v) ? v : z;
+    }
+    if (dec == 2) {
+      int32_t ok = 0;
+      __hip_atomic_compare_exchange_strong(&ss->status, &ok, (int32_t)CAF_E_QUIT,
+                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_dec = (dec == 1 && ld_dev(&ss->status) == CAF_OK) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (s_dec) run_tile(a, d, blockIdx.x, smem, &s_ctr);
+  __syncthreads();
+  if (threadIdx.x == 0) finish_tile(a, d, ntiles, false);
+}
+
+// ---- the mailbox drain ----------------------------------------------------
+
+__device__ __forceinline__ uint32_t group_key(const Desc& e) {
+  switch (e.behavior) {
+    case CAF_BHV_GEMM: {
+      const uint32_t n = e.p.g.n;
+      return n >= 512 ? 0u : n >= 256 ? 1u : n >= 128 ? 2u : n >= 64 ? 3u : 4u;
+    }
+    case CAF_BHV_MANDELBROT: return 5u;
+    case CAF_BHV_TANH: return 6u;
+    case CAF_BHV_ROWSUM: return 7u;
+    default: return 8u;
+  }
+}
+constexpr uint32_t kKeys = 9;
+
+struct DrainLds {
+  uint32_t slot[kMaxBatch];
+  uint32_t nt[kMaxBatch];
+  uint32_t scan[kMaxBatch];  // tile counts by position, then their exclusive prefix
+  uint16_t pos[kMaxBatch];
+  uint8_t key[kMaxBatch];
+  uint8_t dead[kMaxBatch];
+  uint32_t alive[kAliveWords];
+  uint32_t hist[kKeys];
+  uint32_t running[kKeys];
+  uint32_t wave_cnt[4][kKeys];
+  uint32_t wave_sum[4];
+  uint64_t d, cnt, pub, done;
+  uint32_t total;
+};
+static_assert(sizeof(DrainLds) <= kSmemBytes, "drain scratch fits the tile LDS");
+
+// In-place exclusive prefix sum of v[0..count), count <= 1024, whole workgroup.
+__device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* wave_sum) {
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
+  uint32_t loc[4];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t idx = t * 4 + i;
+    loc[i] = idx < count ? v[idx] : 0u;
+    s += loc[i];
+  }
+  uint32_t incl = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off);
+    if (lane >= (uint32_t)off) incl += o;
+  }
+  if (lane == 63) wave_sum[w] = incl;
+  __syncthreads();
+  uint32_t wbase = 0, total = 0;
+  for (uint32_t i = 0; i < 4; ++i) {
+    if (i < w) wbase += wave_sum[i];
+    total += wave_sum[i];
+  }
+  uint32_t run = wbase + incl - s;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t idx = t * 4 + i;
+    if (idx < count) v[idx] = run;
+    run += loc[i];
+  }
+  __syncthreads();
+  return total;
+}
+
+// Drains one batch from the mailbox (whole workgroup; the caller holds the
+// drain lock, which is released here).  Returns true if anything was drained.
+// Kept out of line so its registers do not add to the tile loop's.
+__device__ __noinline__ bool drain_once(const KArgs& a, DrainLds& L) {
+  const uint32_t t = threadIdx.x;
+  if (t == 0) {
+    const uint64_t tail = ld_sys_acq(&a.hctl->tail);
+    const uint64_t d = ld_dev_acq(&a.dctl->drained);
+    const uint64_t avail = tail - d;
+    L.d = d;
+    L.cnt = avail < a.max_batch ? avail : a.max_batch;
+    L.pub = ld_dev_acq(&a.dctl->tiles_pub);
+    L.done = ld_dev_acq(&a.dctl->tiles_done);
+    if (ld_sys(&a.hctl->stop)) st_dev(&a.dctl->stop_seen, 1u);
+  }
+  if (t < kKeys) L.hist[t] = 0;
+  __syncthreads();
+  uint32_t cnt = (uint32_t)L.cnt;
+  if (cnt == 0) {
+    if (t == 0) unlock_drain(a);
+    return false;
+  }
+  if (t < kAliveWords) L.alive[t] = ld_sys(&a.hctl->alive[t]);
+  __syncthreads();
+  // Copy the entries into their device slots.
+  for (uint32_t i = t; i < cnt; i += kThreads) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&a.hring[(L.d + i) % a.cap]);
+    Desc e;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(&e);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dst[q] = ld_sys(src + q);
+    const bool alive = (L.alive[e.actor >> 5] >> (e.actor & 31)) & 1u;
+    const uint32_t slot = e.slot;
+    a.slots[slot].d = e;
+    L.slot[i] = slot;
+    L.nt[i] = alive ? desc_ntiles(e) : 0u;
+    L.dead[i] = alive ? 0 : 1;
+    L.key[i] = (uint8_t)(a.grouping == CAF_GROUP_LPT ? group_key(e) : 0u);
+  }
+  __syncthreads();
+  // Flow control: keep the tile map ahead of the slowest reader by tcap/2.
+  for (uint32_t i = t; i < cnt; i += kThreads) L.scan[i] = L.nt[i];
+  __syncthreads();
+  uint32_t total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
+  const uint64_t room = a.tcap / 2 - (L.pub - L.done);
+  if (total > room) {
+    if (t == 0) {
+      uint32_t c = 0;
+      while (c < cnt && (uint64_t)L.scan[c] + L.nt[c] <= room) ++c;
+      L.cnt = c;
+    }
+    __syncthreads();
+    cnt = (uint32_t)L.cnt;
+    if (cnt == 0) {
+      if (t == 0) unlock_drain(a);
+      return false;
+    }
+  }
+  // Grouping: stable counting sort of the batch by key.
+  if (a.grouping == CAF_GROUP_LPT) {
+    for (uint32_t i = t; i < cnt; i += kThreads) atomicAdd(&L.hist[L.key[i]], 1u);
+    __syncthreads();
+    if (t == 0) {
+      uint32_t run = 0;
+      for (uint32_t k = 0; k < kKeys; ++k) {
+        L.running[k] = run;
+        run += L.hist[k];
+      }
+    }
+    __syncthreads();
+    const uint32_t lane = lane_id(), w = wave_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t c0 = 0; c0 < cnt; c0 += kThreads) {
+      const uint32_t i = c0 + t;
+      const bool valid = i < cnt;
+      const uint32_t k = valid ? L.key[i] : kKeys;
+      uint32_t rank = 0;
+      for (uint32_t kk = 0; kk < kKeys; ++kk) {
+        const uint64_t m = __ballot(valid && k == kk);
+        if (k == kk) rank = __popcll(m & lt_mask);
+        if (lane == 0) L.wave_cnt[w][kk] = __popcll(m);
+      }
+      __syncthreads();
+      uint32_t off = 0;
+      if (valid) {
+        off = L.running[k];
+        for (uint32_t ww = 0; ww < w; ++ww) off += L.wave_cnt[ww][k];
+      }
+      __syncthreads();
+      if (t < kKeys)
+        for (uint32_t ww = 0; ww < 4; ++ww) L.running[t] += L.wave_cnt[ww][t];
+      if (valid) L.pos[i] = (uint16_t)(off + rank);
+      __syncthreads();
+    }
+  } else {
+    for (uint32_t i = t; i < cnt; i += kThreads) L.pos[i] = (uint16_t)i;
+  }
+  __syncthreads();
+  // Prefix of tile counts in work order.
+  for (uint32_t i = t; i < cnt; i += kThreads) L.scan[L.pos[i]] = L.nt[i];
+  __syncthreads();
+  total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
+  const uint64_t pub = L.pub;
+  for (uint32_t i = t; i < cnt; i += kThreads) {
+    const uint32_t slot = L.slot[i], nt = L.nt[i];
+    const uint64_t base = pub + L.scan[L.pos[i]];
+    a.slots[slot].tile_base = base;
+    a.slots[slot].ntiles = nt;
+    for (uint32_t k = 0; k < nt; ++k) a.tile2slot[(base + k) % a.tcap] = slot;
+    if (L.dead[i]) write_completion(a, a.slots[slot].d.req_id, CAF_E_QUIT, nullptr);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (t == 0) {
+    st_dev_rel(&a.dctl->tiles_pub, pub + total);
+    st_dev_rel(&a.dctl->drained, L.d + cnt);
+    st_sys_rel(&a.hctl->drained, L.d + cnt);
+    unlock_drain(a);
+  }
+  return true;
+}
+
+// Claims the next published tile (thread-level).
+__device__ bool try_claim(const KArgs& a, uint64_t& g) {
+  uint64_t pub = ld_dev_acq(&a.dctl->tiles_pub);
+  uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
+  while (cur < pub) {
+    if (cas_dev(&a.dctl->tiles_claimed, cur, cur + 1)) {
+      g = cur;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    pub = ld_dev_acq(&a.dctl->tiles_pub);
+  }
+  return false;
+}
+
+enum : uint32_t { CMD_IDLE = 0, CMD_TILE = 1, CMD_DRAIN = 2 };
+
+__global__ void __launch_bounds__(kThreads) drain_kernel(KArgs a) {
+  __shared__ __align__(16) uint8_t smem[kSmemBytes];
+  __shared__ __align__(16) DevSlot s_slot;
+  __shared__ uint32_t s_cmd, s_exit, s_ctr;
+  __shared__ uint64_t s_g;
+  const uint32_t t = threadIdx.x;
+  uint64_t last_work = now_ticks();
+  uint32_t idle_rounds = 0;
+  for (;;) {
+    if (t == 0) {
+      uint64_t g;
+      if (try_claim(a, g)) {
+        s_cmd = CMD_TILE;
+        s_g = g;
+      } else if (lock_drain(a, false)) {
+        s_cmd = CMD_DRAIN;
+      } else {
+        s_cmd = CMD_IDLE;
+      }
+    }
+    __syncthreads();
+    const uint32_t cmd = s_cmd;
+    if (cmd == CMD_TILE) {
+      const uint64_t g = s_g;
+      if (t == 0) {
+        const uint32_t slot = ld_dev(&a.tile2slot[g % a.tcap]);
+        s_slot = a.slots[slot];
+      }
+      __syncthreads();
+      // The descriptor is the same for every lane: move it to scalar
+      // registers so the tile code sees uniform parameters.
+      Desc d;
+      {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&s_slot.d);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&d);
+#pragma unroll
+        for (int q = 0; q < (int)(sizeof(Desc) / 4); ++q)
+          dst[q] = __builtin_amdgcn_readfirstlane(src[q]);
+      }
+      const uint32_t ntiles = __builtin_amdgcn_readfirstlane(s_slot.ntiles);
+      const uint32_t tile = (uint32_t)(g - s_slot.tile_base);
+      if (ld_dev(&a.sstate[d.slot].status) == CAF_OK) run_tile(a, d, tile, smem, &s_ctr);
+      __syncthreads();
+      if (t == 0) finish_tile(a, d, ntiles, true);
+      __syncthreads();
+      last_work = now_ticks();
+      idle_rounds = 0;
+      continue;
+    }
+    if (cmd == CMD_DRAIN) {
+      const bool got = drain_once(a, *reinterpret_cast<DrainLds*>(smem));
+      __syncthreads();
+      if (got) {
+        last_work = now_ticks();
+        idle_rounds = 0;
+        continue;
+      }
+    }
+    if (t == 0) {
+      uint32_t ex = 0;
+      if (ld_dev(&a.dctl->stop_seen)) {
+        ex = 1;
+      } else if (a.exit_on_empty) {
+        if (ld_dev(&a.dctl->tiles_claimed) >= ld_dev_acq(&a.dctl->tiles_pub) &&
+            ld_dev(&a.dctl->drain_lock) == 0 &&
+            ld_sys_acq(&a.hctl->tail) == ld_dev_acq(&a.dctl->drained) &&
+            ld_dev(&a.dctl->tiles_claimed) >= ld_dev_acq(&a.dctl->tiles_pub))
+          ex = 1;
+      } else if (now_ticks() - last_work > a.idle_ticks) {
+        ex = 1;
+      }
+      s_exit = ex;
+      if (!ex) {
+        idle_rounds = idle_rounds < 8 ? idle_rounds + 1 : 8;
+        backoff_sleep(idle_rounds);
+      }
+    }
+    __syncthreads();
+    if (s_exit) break;
+  }
+  if (t == 0) {
+    const uint32_t prev = __hip_atomic_fetch_add(&a.dctl->wg_exited, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == a.grid) {
+      st_dev(&a.dctl->wg_exited, 0u);
+      st_sys_rel(&a.hctl->exited_gen, a.gen);
+    }
+  }
+}
+
+// ---- host-side launch wrappers ------------------------------------------
+
+hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(plain_kernel, dim3(ntiles), dim3(kThreads), 0, s, a, d, ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_drain(const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(drain_kernel, dim3(a.grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t drain_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel, kThreads, 0);
+}
+
+}  // namespace cafgpu

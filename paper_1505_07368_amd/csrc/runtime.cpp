@@ -1,0 +1,953 @@
+// Host runtime of the compute actor and the C ABI of include/caf_gpu.h.
+//
+// The host side owns: the actor table (behaviour, signature, forwarding
+// target, alive flag), request ids and futures, the slot pool and the
+// arena sub-allocator that enforce the HBM budget (admission), the mailbox
+// ring writer, the drain-kernel launcher, and one poller thread that turns
+// completion records into resolved futures exactly once.
+//
+// Paper correspondence: spawn_cl and the OpenCL actor (Sec. 4.6), typed
+// interfaces checked per message (Sec. 4.5), sync_send / then with unique
+// request ids, errors and timeouts (Sec. 5), call-by-value messages
+// (Sec. 4.4), the actor life cycle and max_msgs per run (Sec. 6).
+#include <hip/hip_runtime.h>
+#include <immintrin.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "caf_internal.h"
+
+namespace cafgpu {
+hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s);
+hipError_t launch_drain(const KArgs& a, hipStream_t s);
+hipError_t drain_occupancy(int* blocks_per_cu);
+}  // namespace cafgpu
+
+using namespace cafgpu;
+
+namespace {
+
+constexpr uint64_t kGranule = 256;
+constexpr uint32_t kTileMapCap = 1u << 22;
+
+inline int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Best-fit sub-allocator over the caller's arena, with coalescing.
+class Arena {
+ public:
+  void init(uint64_t base, uint64_t bytes) {
+    base_ = base;
+    size_ = bytes / kGranule * kGranule;
+    by_off_.clear();
+    by_size_.clear();
+    insert(0, size_);
+  }
+  bool alloc(uint64_t bytes, uint64_t* addr) {
+    uint64_t need = (bytes + kGranule - 1) / kGranule * kGranule;
+    if (need == 0) need = kGranule;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = by_size_.lower_bound(need);
+    if (it == by_size_.end()) return false;
+    uint64_t sz = it->first, off = it->second;
+    erase(off, sz);
+    if (sz > need) insert(off + need, sz - need);
+    in_use_ += need;
+    if (in_use_ > peak_) peak_ = in_use_;
+    *addr = base_ + off;
+    return true;
+  }
+  void free(uint64_t addr, uint64_t bytes) {
+    uint64_t need = (bytes + kGranule - 1) / kGranule * kGranule;
+    if (need == 0) need = kGranule;
+    std::lock_guard<std::mutex> g(mu_);
+    uint64_t off = addr - base_, sz = need;
+    in_use_ -= need;
+    auto nx = by_off_.lower_bound(off);
+    if (nx != by_off_.end() && nx->first == off + sz) {
+      uint64_t nsz = nx->second;
+      erase(nx->first, nsz);
+      sz += nsz;
+    }
+    auto pv = by_off_.lower_bound(off);
+    if (pv != by_off_.begin()) {
+      --pv;
+      if (pv->first + pv->second == off) {
+        uint64_t poff = pv->first, psz = pv->second;
+        erase(poff, psz);
+        off = poff;
+        sz += psz;
+      }
+    }
+    insert(off, sz);
+  }
+  uint64_t in_use() {
+    std::lock_guard<std::mutex> g(mu_);
+    return in_use_;
+  }
+  uint64_t peak() {
+    std::lock_guard<std::mutex> g(mu_);
+    return peak_;
+  }
+
+ private:
+  void insert(uint64_t off, uint64_t sz) {
+    by_off_[off] = sz;
+    by_size_.emplace(sz, off);
+  }
+  void erase(uint64_t off, uint64_t sz) {
+    by_off_.erase(off);
+    auto r = by_size_.equal_range(sz);
+    for (auto i = r.first; i != r.second; ++i)
+      if (i->second == off) {
+        by_size_.erase(i);
+        break;
+      }
+  }
+  std::mutex mu_;
+  uint64_t base_ = 0, size_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<uint64_t, uint64_t> by_off_;
+  std::multimap<uint64_t, uint64_t> by_size_;
+};
+
+struct Block {
+  uint64_t addr = 0, bytes = 0;
+};
+
+struct ActorRec {
+  int32_t behavior = -1;
+  caf_spawn_args spawn{};
+  bool alive = false;
+  uint32_t seq = 0;  // next per-actor sequence number
+};
+
+size_t dtype_bytes(int32_t dt) {
+  switch (dt) {
+    case CAF_I32: return 4;
+    case CAF_U16: return 2;
+    case CAF_F32: return 4;
+    case CAF_F64: return 8;
+    case CAF_BF16: return 2;
+    case CAF_U64: return 8;
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct caf_future {
+  caf_gpu_system* sys = nullptr;
+  uint64_t req_id = 0;
+  std::atomic<int> state{0};  // 0 pending, 1 replied, 2 gave up (timeout)
+  int32_t status = 0;
+  caf_buf result{};
+  uint8_t inline_data[kInlineBytes] = {};
+  Block out;                  // arena reply buffer owned by this future
+  std::atomic<int> refs{2};   // the caller's handle + the request in flight
+  int64_t t_issue = 0, t_done = 0;
+};
+
+struct SlotInfo {
+  uint64_t req_id = 0;
+  caf_future* fut = nullptr;
+  std::vector<Block> temps;  // staged inputs, intermediate replies, unwanted replies
+};
+
+struct caf_gpu_system {
+  caf_gpu_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr, dstream = nullptr;
+  bool own_stream = false, own_dstream = false;
+  // host memory shared with the device
+  HostCtl* hctl = nullptr;
+  Desc* hring = nullptr;
+  Comp* comp = nullptr;
+  // device memory
+  DevCtl* dctl = nullptr;
+  DevSlot* dslots = nullptr;
+  SlotState* sstate = nullptr;
+  uint32_t* tile2slot = nullptr;
+  DevActor* dactors = nullptr;
+  KArgs kargs{};
+  Arena arena;
+  uint32_t cap = 0;
+  // actor table, slots, mailbox
+  std::mutex mu;
+  std::condition_variable cv_space;
+  std::vector<ActorRec> actors;
+  std::vector<SlotInfo> slots;
+  std::vector<uint32_t> free_slots;
+  uint64_t tail = 0;
+  uint64_t req_seq = 1;
+  std::atomic<uint64_t> outstanding{0};
+  // drain kernel
+  std::mutex launch_mu;
+  uint32_t launched_gen = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  // poller
+  std::thread poller;
+  std::atomic<bool> stop_poller{false};
+  uint64_t comp_head = 0;
+  std::atomic<uint64_t> st_requests{0}, st_sends{0}, st_completions{0}, st_launches{0},
+      st_drain_launches{0}, st_dup{0}, st_swallowed{0}, st_rejected{0};
+  uint32_t mandel_tile_px = 1024;
+  uint32_t gemm_tile = 0;
+  bool shut = false;
+};
+
+namespace {
+
+void put_ref(caf_future* f) {
+  if (f->refs.fetch_sub(1) == 1) {
+    if (f->out.bytes) f->sys->arena.free(f->out.addr, f->out.bytes);
+    delete f;
+  }
+}
+
+bool drain_running(caf_gpu_system* s) {
+  return __atomic_load_n(&s->hctl->exited_gen, __ATOMIC_ACQUIRE) != s->launched_gen;
+}
+
+// Launches the drain kernel if it is not running (ring modes).
+void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
+  std::lock_guard<std::mutex> g(s->launch_mu);
+  if (drain_running(s)) return;
+  if (only_if_pending &&
+      __atomic_load_n(&s->hctl->drained, __ATOMIC_ACQUIRE) >=
+          __atomic_load_n(&s->hctl->tail, __ATOMIC_ACQUIRE))
+    return;
+  KArgs a = s->kargs;
+  a.gen = ++s->launched_gen;
+  // Launch windows are timed with events until the pool is full.
+  if (s->ev_used == s->ev_pool.size() && s->ev_pool.size() < 16384) {
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    s->ev_pool.emplace_back(e0, e1);
+  }
+  const bool timed = s->ev_used < s->ev_pool.size();
+  if (timed) hipEventRecord(s->ev_pool[s->ev_used].first, s->dstream);
+  hipError_t e = launch_drain(a, s->dstream);
+  if (e != hipSuccess) std::fprintf(stderr, "cafgpu: drain launch failed: %s\n", hipGetErrorString(e));
+  if (timed) hipEventRecord(s->ev_pool[s->ev_used++].second, s->dstream);
+  s->st_drain_launches++;
+}
+
+void resolve_slot(caf_gpu_system* s, const Comp& c) {
+  const uint32_t slot = (uint32_t)(c.req_id & (kMaxSlots - 1));
+  caf_future* f = nullptr;
+  std::vector<Block> temps;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (slot >= s->cap || s->slots[slot].req_id != c.req_id) {
+      s->st_dup++;
+      return;
+    }
+    SlotInfo& si = s->slots[slot];
+    f = si.fut;
+    temps.swap(si.temps);
+    si.fut = nullptr;
+    si.req_id = 0;
+    s->free_slots.push_back(slot);
+  }
+  for (auto& b : temps) s->arena.free(b.addr, b.bytes);
+  s->st_completions++;
+  if (f) {
+    f->status = c.status;
+    if (f->result.on_device == 0 && f->result.data == f->inline_data)
+      std::memcpy(f->inline_data, c.data, kInlineBytes);
+    f->t_done = now_ns();
+    int expect = 0;
+    if (!f->state.compare_exchange_strong(expect, 1)) s->st_swallowed++;
+    put_ref(f);
+  }
+  s->outstanding.fetch_sub(1);
+  s->cv_space.notify_all();
+}
+
+void poller_main(caf_gpu_system* s) {
+  hipSetDevice(s->device);
+  uint32_t idle = 0;
+  const uint32_t ccap = s->cap;
+  while (!s->stop_poller.load(std::memory_order_relaxed)) {
+    Comp* c = &s->comp[s->comp_head % ccap];
+    const uint32_t lap = (uint32_t)(s->comp_head / ccap) + 1;
+    if (__atomic_load_n(&c->lap, __ATOMIC_ACQUIRE) == lap) {
+      Comp copy;
+      std::memcpy(&copy, c, sizeof copy);
+      s->comp_head++;
+      resolve_slot(s, copy);
+      idle = 0;
+      continue;
+    }
+    if (s->cfg.mode != CAF_MODE_PLAIN && (idle & 63) == 0) ensure_drain(s, true);
+    ++idle;
+    if (idle < 20000 || s->outstanding.load() != 0) {
+      _mm_pause();
+    } else {
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+  }
+}
+
+// Reply element type / count of a behaviour, and signature checks.
+struct Shape {
+  int32_t dtype = CAF_F32;
+  uint64_t numel = 0;
+  uint32_t rows = 0, cols = 0;  // shape handed to a forwarded stage
+};
+
+int check_stage_input(const ActorRec& a, uint32_t rows, uint32_t cols, Shape* out) {
+  if (a.behavior == CAF_BHV_TANH) {
+    if (a.spawn.n && (a.spawn.n != rows || a.spawn.n != cols)) return CAF_E_INVALID;
+    *out = Shape{CAF_F32, (uint64_t)rows * cols, rows, cols};
+    return CAF_OK;
+  }
+  if (a.behavior == CAF_BHV_ROWSUM) {
+    if (a.spawn.n && (a.spawn.n != rows || a.spawn.n != cols)) return CAF_E_INVALID;
+    *out = Shape{CAF_F32, rows, rows, 1};
+    return CAF_OK;
+  }
+  return CAF_E_INVALID;  // only f32 matrix stages can be forwarded to
+}
+
+int check_signature(const ActorRec& a, const void* args, uint64_t args_bytes, const caf_buf* in,
+                    uint32_t n_in, Shape* out) {
+  switch (a.behavior) {
+    case CAF_BHV_NOOP:
+      if (n_in != 1 || !in || in[0].dtype != CAF_I32 || in[0].numel == 0 || !in[0].data)
+        return CAF_E_INVALID;
+      if (in[0].numel > (1u << 30)) return CAF_E_INVALID;
+      *out = Shape{CAF_I32, in[0].numel, 0, 0};
+      return CAF_OK;
+    case CAF_BHV_MANDELBROT: {
+      if (n_in != 0 || args_bytes != sizeof(caf_mandel_args) || !args) return CAF_E_INVALID;
+      const caf_mandel_args* m = (const caf_mandel_args*)args;
+      if (m->max_iter < 1 || m->max_iter > 65535 || m->width == 0) return CAF_E_INVALID;
+      if (m->fp != CAF_F32 && m->fp != CAF_F64) return CAF_E_INVALID;
+      if ((uint64_t)m->row0 + m->rows > m->height) return CAF_E_INVALID;
+      if (m->width > (1u << 20) || m->rows > (1u << 20)) return CAF_E_INVALID;
+      *out = Shape{CAF_U16, (uint64_t)m->rows * m->width, m->rows, m->width};
+      return CAF_OK;
+    }
+    case CAF_BHV_GEMM: {
+      if (args_bytes != sizeof(caf_gemm_args) || !args || n_in != 2 || !in) return CAF_E_INVALID;
+      const caf_gemm_args* g = (const caf_gemm_args*)args;
+      if (g->n == 0 || g->n > 16384) return CAF_E_INVALID;
+      if (g->in_dtype != CAF_F32 && g->in_dtype != CAF_BF16) return CAF_E_INVALID;
+      if (a.spawn.n && a.spawn.n != g->n) return CAF_E_INVALID;
+      const uint64_t nn = (uint64_t)g->n * g->n;
+      for (int i = 0; i < 2; ++i)
+        if (in[i].dtype != g->in_dtype || in[i].numel != nn || !in[i].data) return CAF_E_INVALID;
+      *out = Shape{CAF_F32, nn, g->n, g->n};
+      return CAF_OK;
+    }
+    case CAF_BHV_TANH:
+    case CAF_BHV_ROWSUM: {
+      if (args_bytes != sizeof(caf_shape_args) || !args || n_in != 1 || !in) return CAF_E_INVALID;
+      const caf_shape_args* sh = (const caf_shape_args*)args;
+      if (sh->rows == 0 || sh->cols == 0) return CAF_E_INVALID;
+      if (in[0].dtype != CAF_F32 || !in[0].data) return CAF_E_INVALID;
+      if (in[0].numel != (uint64_t)sh->rows * sh->cols) return CAF_E_INVALID;
+      return check_stage_input(a, sh->rows, sh->cols, out);
+    }
+    case CAF_BHV_HASHCHAIN:
+      if (n_in != 0 || args_bytes != sizeof(caf_hash_args) || !args) return CAF_E_INVALID;
+      *out = Shape{CAF_U64, 1, 0, 0};
+      return CAF_OK;
+    case CAF_BHV_FAULT:
+      *out = Shape{CAF_I32, 0, 0, 0};
+      return CAF_OK;
+  }
+  return CAF_E_INVALID;
+}
+
+uint32_t gemm_tile_for(const caf_gpu_system* s, uint32_t n) {
+  if (s->gemm_tile == 64 || s->gemm_tile == 128) return s->gemm_tile;
+  return n <= 128 ? 64u : 128u;
+}
+
+int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
+           uint64_t args_bytes, const caf_buf* in, uint32_t n_in, const caf_buf* out_buf,
+           caf_actor forward_to, caf_future** fut, bool is_request) {
+  if (!s || s->shut) return CAF_E_INVALID;
+  if (n_in > 2) return CAF_E_INVALID;
+  ActorRec a, hop[kMaxHops];
+  uint32_t nhops = 0;
+  Shape sh, hsh[kMaxHops];
+  uint32_t aidx = 0, hidx[kMaxHops] = {0, 0};
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (dst == 0 || dst > s->actors.size()) return CAF_E_NO_ACTOR;
+    aidx = (uint32_t)(dst - 1);
+    a = s->actors[aidx];
+    if (!a.alive) return CAF_E_NO_ACTOR;
+    int st = check_signature(a, args, args_bytes, in, n_in, &sh);
+    if (st != CAF_OK) return st;
+    caf_actor next = forward_to ? forward_to : a.spawn.forward_to;
+    Shape prev = sh;
+    while (next) {
+      if (nhops == kMaxHops) return CAF_E_INVALID;
+      if (next > s->actors.size()) return CAF_E_NO_ACTOR;
+      const ActorRec& h = s->actors[next - 1];
+      if (!h.alive) return CAF_E_NO_ACTOR;
+      if (prev.dtype != CAF_F32 || prev.rows == 0) return CAF_E_INVALID;
+      st = check_stage_input(h, prev.rows, prev.cols, &hsh[nhops]);
+      if (st != CAF_OK) return st;
+      hidx[nhops] = (uint32_t)(next - 1);
+      hop[nhops] = h;
+      prev = hsh[nhops];
+      ++nhops;
+      next = h.spawn.forward_to;
+    }
+  }
+  const Shape& final_shape = nhops ? hsh[nhops - 1] : sh;
+  const uint64_t final_bytes = final_shape.numel * dtype_bytes(final_shape.dtype);
+  bool inline_in = false, inline_out = false;
+  if (a.behavior == CAF_BHV_NOOP) {
+    inline_in = !in[0].on_device && in[0].numel * 4 <= kInlineBytes;
+  }
+  if (nhops == 0 && (a.behavior == CAF_BHV_NOOP || a.behavior == CAF_BHV_HASHCHAIN) &&
+      final_bytes <= kInlineBytes && (!out_buf || !out_buf->data))
+    inline_out = true;
+  if (out_buf && out_buf->data) {
+    if (!out_buf->on_device || out_buf->dtype != final_shape.dtype ||
+        out_buf->numel != final_shape.numel)
+      return CAF_E_INVALID;
+  }
+
+  // Descriptor (everything except slot, seq and request id).
+  Desc d;
+  std::memset(&d, 0, sizeof d);
+  d.actor = aidx;
+  d.behavior = (uint16_t)a.behavior;
+  switch (a.behavior) {
+    case CAF_BHV_MANDELBROT: {
+      const caf_mandel_args* m = (const caf_mandel_args*)args;
+      if (m->fp == CAF_F64) {
+        d.flags |= DF_FP64;
+        d.p.m64.re_min = m->re_min;
+        d.p.m64.im_min = m->im_min;
+        d.p.m64.step_re = m->step_re;
+        d.p.m64.step_im = m->step_im;
+      } else {
+        // float messages: the viewport doubles are rounded to float once
+        d.p.m32.re_min = (float)m->re_min;
+        d.p.m32.im_min = (float)m->im_min;
+        d.p.m32.step_re = (float)m->step_re;
+        d.p.m32.step_im = (float)m->step_im;
+      }
+      d.p.m64.width = m->width;
+      d.p.m64.row0 = m->row0;
+      d.p.m64.rows = m->rows;
+      d.p.m64.max_iter = m->max_iter;
+      d.tcfg = s->mandel_tile_px;
+      break;
+    }
+    case CAF_BHV_GEMM: {
+      const caf_gemm_args* g = (const caf_gemm_args*)args;
+      if (g->in_dtype == CAF_BF16) d.flags |= DF_BF16;
+      d.p.g.n = g->n;
+      d.tcfg = gemm_tile_for(s, g->n);
+      break;
+    }
+    case CAF_BHV_TANH:
+    case CAF_BHV_ROWSUM: {
+      const caf_shape_args* x = (const caf_shape_args*)args;
+      d.p.s.rows = x->rows;
+      d.p.s.cols = x->cols;
+      break;
+    }
+    case CAF_BHV_HASHCHAIN:
+      d.p.h.x = ((const caf_hash_args*)args)->x;
+      break;
+    case CAF_BHV_NOOP:
+      d.numel = (uint32_t)in[0].numel;
+      if (inline_in) {
+        d.flags |= DF_INLINE_IN;
+        std::memcpy(d.p.raw, in[0].data, in[0].numel * 4);
+      }
+      break;
+    default:
+      break;
+  }
+  if (inline_out) d.flags |= DF_INLINE_OUT;
+  if (!is_request) d.flags |= DF_SEND;
+  if (desc_ntiles(d) > kTileMapCap / 4) return CAF_E_INVALID;
+  for (uint32_t h = 0; h < nhops; ++h)
+    d.hop_actor[h] = ((uint32_t)hop[h].behavior << 16) | (hidx[h] + 1);
+
+  // Admission: a slot plus every arena buffer the message needs.
+  std::vector<Block> blocks;  // staged inputs, stage outputs
+  Block out_blk;              // final reply when library-allocated (owned by the future)
+  uint32_t slot = 0;
+  uint64_t stage_out[1 + kMaxHops] = {0, 0, 0};
+  {
+    std::unique_lock<std::mutex> g(s->mu);
+    for (;;) {
+      bool ok = !s->free_slots.empty();
+      auto take = [&](uint64_t bytes, Block* b) {
+        if (!ok) return;
+        uint64_t addr;
+        if (!s->arena.alloc(bytes, &addr)) {
+          ok = false;
+          return;
+        }
+        b->addr = addr;
+        b->bytes = bytes;
+      };
+      // inputs from host memory are staged into the arena
+      Block staged[2];
+      for (uint32_t i = 0; i < n_in; ++i)
+        if (!in[i].on_device && !(inline_in && i == 0))
+          take(in[i].numel * dtype_bytes(in[i].dtype), &staged[i]);
+      // stage outputs: stage 0 .. nhops; the last one is the reply
+      Block sout[1 + kMaxHops];
+      for (uint32_t k = 0; k <= nhops; ++k) {
+        const Shape& shk = k == 0 ? sh : hsh[k - 1];
+        const uint64_t bytes = shk.numel * dtype_bytes(shk.dtype);
+        const bool last = k == nhops;
+        if (last && (inline_out || (out_buf && out_buf->data))) continue;
+        take(bytes ? bytes : 4, &sout[k]);
+      }
+      if (ok) {
+        slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        for (uint32_t i = 0; i < 2; ++i)
+          if (staged[i].bytes) blocks.push_back(staged[i]);
+        for (uint32_t k = 0; k <= nhops; ++k) {
+          if (!sout[k].bytes) continue;
+          stage_out[k] = sout[k].addr;
+          if (k == nhops && is_request) out_blk = sout[k];
+          else blocks.push_back(sout[k]);
+        }
+        break;
+      }
+      for (uint32_t i = 0; i < 2; ++i)
+        if (staged[i].bytes) s->arena.free(staged[i].addr, staged[i].bytes);
+      for (uint32_t k = 0; k <= nhops; ++k)
+        if (sout[k].bytes) s->arena.free(sout[k].addr, sout[k].bytes);
+      if (!s->cfg.blocking) {
+        s->st_rejected++;
+        return CAF_E_OVERLOAD;
+      }
+      s->cv_space.wait_for(g, std::chrono::milliseconds(1));
+      if (s->shut) return CAF_E_QUIT;
+    }
+  }
+  if (out_buf && out_buf->data) stage_out[nhops] = (uint64_t)(uintptr_t)out_buf->data;
+
+  // Inputs: device pointers as given, host inputs copied (synchronously,
+  // before the message becomes visible to the device).
+  uint64_t inptr[2] = {0, 0};
+  {
+    size_t bi = 0;
+    for (uint32_t i = 0; i < n_in; ++i) {
+      if (inline_in && i == 0) continue;
+      if (in[i].on_device) {
+        inptr[i] = (uint64_t)(uintptr_t)in[i].data;
+      } else {
+        const Block& b = blocks[bi++];
+        inptr[i] = b.addr;
+        hipError_t e = hipMemcpy((void*)(uintptr_t)b.addr, in[i].data,
+                                 in[i].numel * dtype_bytes(in[i].dtype), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+          std::lock_guard<std::mutex> g(s->mu);
+          for (auto& bb : blocks) s->arena.free(bb.addr, bb.bytes);
+          if (out_blk.bytes) s->arena.free(out_blk.addr, out_blk.bytes);
+          s->free_slots.push_back(slot);
+          return CAF_E_DEVICE;
+        }
+      }
+    }
+  }
+  d.in0 = inptr[0];
+  d.in1 = inptr[1];
+  d.out = stage_out[0];
+  for (uint32_t h = 0; h < nhops; ++h) d.hop_out[h] = stage_out[h + 1];
+
+  caf_future* f = nullptr;
+  if (is_request) {
+    f = new caf_future();
+    f->sys = s;
+    f->out = out_blk;
+    f->result.dtype = final_shape.dtype;
+    f->result.numel = final_shape.numel;
+    if (inline_out) {
+      f->result.data = f->inline_data;
+      f->result.on_device = 0;
+    } else {
+      f->result.data = (void*)(uintptr_t)stage_out[nhops];
+      f->result.on_device = 1;
+    }
+  }
+
+  // Enqueue in call order: the mailbox is FIFO per (sender, actor).
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    ActorRec& ar = s->actors[aidx];
+    if (!ar.alive) {
+      for (auto& b : blocks) s->arena.free(b.addr, b.bytes);
+      s->free_slots.push_back(slot);
+      if (f) {
+        if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
+        delete f;
+      }
+      return CAF_E_NO_ACTOR;
+    }
+    const uint64_t rid = (s->req_seq++ << kSlotBits) | slot;
+    d.req_id = rid;
+    d.slot = slot;
+    d.seq = ar.seq++;
+    SlotInfo& si = s->slots[slot];
+    si.req_id = rid;
+    si.fut = f;
+    si.temps = std::move(blocks);
+    if (f) {
+      f->req_id = rid;
+      f->t_issue = now_ns();
+    }
+    s->outstanding.fetch_add(1);
+    if (is_request) s->st_requests++;
+    else s->st_sends++;
+    if (s->cfg.mode == CAF_MODE_PLAIN) {
+      // One launch per stage; stages of a pipeline follow in stream order.
+      for (uint32_t k = 0; k <= nhops; ++k) {
+        Desc sd = d;
+        if (k > 0) {
+          const Shape& ps = k == 1 ? sh : hsh[k - 2];
+          sd.actor = hidx[k - 1];
+          sd.behavior = (uint16_t)hop[k - 1].behavior;
+          sd.in0 = stage_out[k - 1];
+          sd.in1 = 0;
+          sd.out = stage_out[k];
+          std::memset(sd.p.raw, 0, sizeof sd.p.raw);
+          sd.p.s.rows = ps.rows;
+          sd.p.s.cols = ps.cols;
+          sd.flags = (uint16_t)(d.flags & DF_SEND);
+          sd.tcfg = 0;
+          sd.seq = s->actors[hidx[k - 1]].seq++;
+        }
+        sd.hop_actor[0] = sd.hop_actor[1] = 0;
+        if (k < nhops) sd.flags |= DF_NO_COMPLETE;
+        hipError_t e = launch_plain(s->kargs, sd, desc_ntiles(sd), s->stream);
+        s->st_launches++;
+        if (e != hipSuccess) {
+          std::fprintf(stderr, "cafgpu: launch failed: %s\n", hipGetErrorString(e));
+        }
+      }
+    } else {
+      Desc* slotp = &s->hring[s->tail % s->cap];
+      std::memcpy(slotp, &d, sizeof d);
+      s->tail += 1;
+      __atomic_store_n(&s->hctl->tail, s->tail, __ATOMIC_RELEASE);
+    }
+  }
+  if (s->cfg.mode != CAF_MODE_PLAIN) ensure_drain(s, false);
+  if (fut) *fut = f;
+  return CAF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* caf_gpu_strerror(int st) {
+  switch (st) {
+    case CAF_OK: return "ok";
+    case CAF_E_INVALID: return "invalid argument or signature mismatch";
+    case CAF_E_NO_ACTOR: return "no such actor (or it quit)";
+    case CAF_E_OVERLOAD: return "admission refused: HBM budget or mailbox full";
+    case CAF_E_TIMEOUT: return "timed out";
+    case CAF_E_DEVICE: return "device error";
+    case CAF_E_QUIT: return "actor quit before handling the message";
+    case CAF_E_FAULT: return "handler reported failure";
+  }
+  return "unknown status";
+}
+
+int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
+  if (!cfg || !out || !cfg->arena || cfg->arena_bytes < (1u << 16)) return CAF_E_INVALID;
+  if (cfg->mode < CAF_MODE_PLAIN || cfg->mode > CAF_MODE_PERSISTENT) return CAF_E_INVALID;
+  const uint32_t cap = cfg->ring_slots ? cfg->ring_slots : 4096;
+  const uint32_t mb = cfg->max_batch ? cfg->max_batch : 1024;
+  if (cap < 2 || cap > kMaxSlots || mb > kMaxBatch) return CAF_E_INVALID;
+  const uint32_t mpx = cfg->mandel_tile_px ? cfg->mandel_tile_px : 1024;
+  if (mpx % 256 != 0 || mpx > 65536) return CAF_E_INVALID;
+  if (cfg->gemm_tile != 0 && cfg->gemm_tile != 64 && cfg->gemm_tile != 128) return CAF_E_INVALID;
+  if (hipSetDevice(cfg->device) != hipSuccess) return CAF_E_DEVICE;
+  caf_gpu_system* s = new caf_gpu_system();
+  s->cfg = *cfg;
+  s->device = cfg->device;
+  s->cap = cap;
+  s->mandel_tile_px = mpx;
+  s->gemm_tile = cfg->gemm_tile;
+  s->arena.init((uint64_t)(uintptr_t)cfg->arena, cfg->arena_bytes);
+  bool ok = true;
+  auto chk = [&](hipError_t e) {
+    if (e != hipSuccess) {
+      std::fprintf(stderr, "cafgpu: init: %s\n", hipGetErrorString(e));
+      ok = false;
+    }
+  };
+  if (cfg->stream) s->stream = (hipStream_t)cfg->stream;
+  else {
+    chk(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    s->own_stream = true;
+  }
+  if (cfg->drain_stream) s->dstream = (hipStream_t)cfg->drain_stream;
+  else {
+    chk(hipStreamCreateWithFlags(&s->dstream, hipStreamNonBlocking));
+    s->own_dstream = true;
+  }
+  const unsigned hflags = hipHostMallocCoherent | hipHostMallocMapped;
+  chk(hipHostMalloc((void**)&s->hctl, sizeof(HostCtl), hflags));
+  chk(hipHostMalloc((void**)&s->hring, sizeof(Desc) * cap, hflags));
+  chk(hipHostMalloc((void**)&s->comp, sizeof(Comp) * cap, hflags));
+  chk(hipMalloc((void**)&s->dctl, sizeof(DevCtl)));
+  chk(hipMalloc((void**)&s->dslots, sizeof(DevSlot) * cap));
+  chk(hipMalloc((void**)&s->sstate, sizeof(SlotState) * cap));
+  chk(hipMalloc((void**)&s->tile2slot, sizeof(uint32_t) * kTileMapCap));
+  chk(hipMalloc((void**)&s->dactors, sizeof(DevActor) * kMaxActors));
+  if (ok) {
+    std::memset(s->hctl, 0, sizeof(HostCtl));
+    std::memset(s->hring, 0, sizeof(Desc) * cap);
+    std::memset(s->comp, 0, sizeof(Comp) * cap);
+    chk(hipMemset(s->dctl, 0, sizeof(DevCtl)));
+    chk(hipMemset(s->dslots, 0, sizeof(DevSlot) * cap));
+    chk(hipMemset(s->sstate, 0, sizeof(SlotState) * cap));
+    chk(hipMemset(s->dactors, 0, sizeof(DevActor) * kMaxActors));
+    chk(hipDeviceSynchronize());
+  }
+  int rate_khz = 100000;
+  hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, cfg->device);
+  if (rate_khz <= 0) rate_khz = 100000;
+  int cus = 256;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+  int occ = 1;
+  if (ok) chk(drain_occupancy(&occ));
+  if (occ < 1) occ = 1;
+  uint32_t grid = cfg->grid ? cfg->grid : (uint32_t)(cus * (occ < 2 ? occ : 2));
+  if (!ok) {
+    delete s;
+    return CAF_E_DEVICE;
+  }
+  s->actors.reserve(kMaxActors);
+  s->slots.resize(cap);
+  s->free_slots.reserve(cap);
+  for (uint32_t i = 0; i < cap; ++i) s->free_slots.push_back(cap - 1 - i);
+  KArgs& a = s->kargs;
+  a.hctl = s->hctl;
+  a.hring = s->hring;
+  a.comp = s->comp;
+  a.dctl = s->dctl;
+  a.slots = s->dslots;
+  a.sstate = s->sstate;
+  a.tile2slot = s->tile2slot;
+  a.actors = s->dactors;
+  a.cap = cap;
+  a.ccap = cap;
+  a.tcap = kTileMapCap;
+  a.max_batch = mb;
+  const uint64_t idle_us = cfg->idle_exit_us ? cfg->idle_exit_us : 200000;
+  a.idle_ticks = idle_us * (uint64_t)rate_khz / 1000;
+  a.wait_ticks = 2000ull * (uint64_t)rate_khz;  // 2 s
+  a.exit_on_empty = cfg->mode == CAF_MODE_BATCHED ? 1u : 0u;
+  a.grouping = (uint32_t)cfg->grouping;
+  a.grid = grid;
+  s->poller = std::thread(poller_main, s);
+  *out = s;
+  return CAF_OK;
+}
+
+int caf_gpu_spawn(caf_gpu_system* s, int32_t behavior, const caf_spawn_args* args,
+                  caf_actor* out) {
+  if (!s || !out || s->shut) return CAF_E_INVALID;
+  if (behavior < CAF_BHV_NOOP || behavior > CAF_BHV_FAULT) return CAF_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->actors.size() >= kMaxActors) return CAF_E_OVERLOAD;
+  ActorRec a;
+  a.behavior = behavior;
+  if (args) a.spawn = *args;
+  if (a.spawn.forward_to &&
+      (a.spawn.forward_to > s->actors.size() || !s->actors[a.spawn.forward_to - 1].alive))
+    return CAF_E_INVALID;
+  a.alive = true;
+  const uint32_t idx = (uint32_t)s->actors.size();
+  s->actors.push_back(a);
+  __atomic_fetch_or(&s->hctl->alive[idx >> 5], 1u << (idx & 31), __ATOMIC_SEQ_CST);
+  *out = idx + 1;
+  return CAF_OK;
+}
+
+int caf_gpu_send(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
+                 uint64_t args_bytes, const caf_buf* in, uint32_t n_in) {
+  return submit(s, dst, sender, args, args_bytes, in, n_in, nullptr, 0, nullptr, false);
+}
+
+int caf_gpu_request(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
+                    uint64_t args_bytes, const caf_buf* in, uint32_t n_in,
+                    const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut) {
+  if (!fut) return CAF_E_INVALID;
+  *fut = nullptr;
+  return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut, true);
+}
+
+int caf_future_poll(caf_future* f, caf_buf* result, int32_t* reply_status) {
+  if (!f) return CAF_E_INVALID;
+  const int st = f->state.load(std::memory_order_acquire);
+  if (st == 0) return 0;
+  if (st == 2) {
+    if (reply_status) *reply_status = CAF_E_TIMEOUT;
+    if (result) *result = caf_buf{nullptr, 0, f->result.dtype, 0};
+    return 1;
+  }
+  if (reply_status) *reply_status = f->status;
+  if (result) *result = f->result;
+  return 1;
+}
+
+int caf_future_wait(caf_future* f, int64_t timeout_ns, caf_buf* result, int32_t* reply_status) {
+  if (!f) return CAF_E_INVALID;
+  const int64_t t0 = now_ns();
+  uint32_t spins = 0;
+  for (;;) {
+    int r = caf_future_poll(f, result, reply_status);
+    if (r == 1) return f->state.load() == 2 ? CAF_E_TIMEOUT : CAF_OK;
+    if (timeout_ns >= 0 && now_ns() - t0 >= timeout_ns) {
+      int expect = 0;
+      if (f->state.compare_exchange_strong(expect, 2)) {
+        if (reply_status) *reply_status = CAF_E_TIMEOUT;
+        return CAF_E_TIMEOUT;
+      }
+      continue;  // resolved concurrently
+    }
+    if (++spins < 4096) _mm_pause();
+    else std::this_thread::yield();
+  }
+}
+
+uint64_t caf_future_id(const caf_future* f) { return f ? f->req_id : 0; }
+
+void caf_future_release(caf_future* f) {
+  if (f) put_ref(f);
+}
+
+int caf_gpu_quit(caf_gpu_system* s, caf_actor actor, uint32_t /*exit_reason*/) {
+  if (!s) return CAF_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (actor == 0 || actor > s->actors.size() || !s->actors[actor - 1].alive)
+    return CAF_E_NO_ACTOR;
+  const uint32_t idx = (uint32_t)(actor - 1);
+  s->actors[idx].alive = false;
+  __atomic_fetch_and(&s->hctl->alive[idx >> 5], ~(1u << (idx & 31)), __ATOMIC_SEQ_CST);
+  return CAF_OK;
+}
+
+int caf_gpu_drain(caf_gpu_system* s, int64_t timeout_ns) {
+  if (!s) return CAF_E_INVALID;
+  const int64_t t0 = now_ns();
+  uint32_t spins = 0;
+  while (s->outstanding.load() != 0) {
+    if (timeout_ns >= 0 && now_ns() - t0 > timeout_ns) return CAF_E_TIMEOUT;
+    if (++spins < 4096) _mm_pause();
+    else std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  return CAF_OK;
+}
+
+int caf_gpu_get_stats(caf_gpu_system* s, caf_gpu_stats* o) {
+  if (!s || !o) return CAF_E_INVALID;
+  o->requests = s->st_requests;
+  o->sends = s->st_sends;
+  o->completions = s->st_completions;
+  o->launches = s->st_launches;
+  o->drain_launches = s->st_drain_launches;
+  o->duplicate_completions = s->st_dup;
+  o->swallowed = s->st_swallowed;
+  o->arena_in_use = s->arena.in_use();
+  o->arena_peak = s->arena.peak();
+  o->rejected = s->st_rejected;
+  o->device_drained = __atomic_load_n(&s->hctl->drained, __ATOMIC_ACQUIRE);
+  o->outstanding = s->outstanding.load();
+  return CAF_OK;
+}
+
+double caf_gpu_drain_kernel_ms(caf_gpu_system* s, uint64_t* launches) {
+  if (!s) return -1.0;
+  std::lock_guard<std::mutex> g(s->launch_mu);
+  hipStreamSynchronize(s->dstream);
+  double total = 0.0;
+  for (size_t i = 0; i < s->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev_pool[i].first, s->ev_pool[i].second) == hipSuccess)
+      total += ms;
+  }
+  if (launches) *launches = s->ev_used;
+  s->ev_used = 0;
+  return total;
+}
+
+int caf_gpu_shutdown(caf_gpu_system* s) {
+  if (!s) return CAF_E_INVALID;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->shut = true;
+  }
+  s->cv_space.notify_all();
+  __atomic_store_n(&s->hctl->stop, 1u, __ATOMIC_SEQ_CST);
+  hipStreamSynchronize(s->dstream);
+  hipStreamSynchronize(s->stream);
+  // Let the poller collect what the device finished, then stop it.
+  const int64_t t0 = now_ns();
+  while (s->outstanding.load() != 0 && now_ns() - t0 < 200000000LL) std::this_thread::yield();
+  s->stop_poller = true;
+  if (s->poller.joinable()) s->poller.join();
+  // Anything left never reached the device: answer it.
+  for (uint32_t i = 0; i < s->cap; ++i) {
+    SlotInfo& si = s->slots[i];
+    if (!si.req_id) continue;
+    for (auto& b : si.temps) s->arena.free(b.addr, b.bytes);
+    if (si.fut) {
+      si.fut->status = CAF_E_QUIT;
+      int expect = 0;
+      si.fut->state.compare_exchange_strong(expect, 1);
+      put_ref(si.fut);
+    }
+    si = SlotInfo();
+  }
+  for (auto& e : s->ev_pool) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  hipFree(s->dctl);
+  hipFree(s->dslots);
+  hipFree(s->sstate);
+  hipFree(s->tile2slot);
+  hipFree(s->dactors);
+  hipHostFree(s->hctl);
+  hipHostFree(s->hring);
+  hipHostFree(s->comp);
+  if (s->own_stream) hipStreamDestroy(s->stream);
+  if (s->own_dstream) hipStreamDestroy(s->dstream);
+  delete s;
+  return CAF_OK;
+}
+
+}  // extern "C"
+
+// Internal accessors for the load driver.
+int64_t cafgpu_future_issue_ns(const caf_future* f) { return f->t_issue; }
+int64_t cafgpu_future_done_ns(const caf_future* f) { return f->t_done; }

@@ -1,0 +1,371 @@
+// Work-tile functions of the compute actors' behaviours (gfx950).
+//
+// Each function processes one work tile of one message with a 256-thread
+// workgroup (4 wave64s) and returns after its stores are issued; the caller
+// synchronises the workgroup and accounts for the tile.
+//
+// Floating point: this file is compiled with -ffp-contract=off and the
+// pragma below, so no multiply-add is fused and every operation is one
+// IEEE round-to-nearest operation in the type written, in the order
+// written -- the escape-time counts must match the CPU oracle bit for bit.
+#pragma once
+#pragma clang fp contract(off)
+
+#include "caf_internal.h"
+
+namespace cafgpu {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
+__device__ inline uint32_t wave_id() { return threadIdx.x >> 6; }
+
+// ---------------------------------------------------------------------------
+// Mandelbrot escape time (the paper's Mandelbrot workloads, Sec. 7.4 and
+// Sec. 7.5; the recurrence is the textbook set definition, z_0 = 0,
+// z <- z^2 + c, count = first k with |z_k|^2 > 4, else max_iter).
+//
+// A message covers global rows [row0, row0 + rows) of a width-wide image and
+// replies uint16 counts, row-major [rows][width].  Its pixels are cut into
+// 4 x 16 blocks, one block per wave64 at a time (lane -> row lane/16,
+// column lane%16: each row segment is a contiguous 32-byte store), and a
+// work tile is tcfg/64 consecutive blocks.  The waves of the workgroup take
+// blocks of the tile from an LDS counter, so a slow block does not hold the
+// others.  Inside a block every lane iterates its own pixel; the wave
+// leaves the loop as soon as the ballot of lanes that have not escaped is
+// empty -- the early exit is wave-uniform and no lane's count moves past
+// its escape.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ uint32_t escape_count(T cr, T ci, uint32_t max_iter, bool valid) {
+  // live: lanes still iterating, as a wave-wide ballot mask held in scalar
+  // registers.  Lanes that escaped keep computing (their values no longer
+  // matter), so the common path is the nine operations of one iteration
+  // plus scalar bookkeeping; a lane's count is frozen at its first escape,
+  // and the wave exits as soon as the ballot of live lanes is empty.
+  uint64_t live = __builtin_amdgcn_ballot_w64(valid);
+  uint32_t n = max_iter;
+  T zr = T(0), zi = T(0);
+  uint32_t it = 0;
+  if (max_iter == 0 || live == 0) return n;
+  do {
+    T zr2 = zr * zr;
+    T zi2 = zi * zi;
+    T mag = zr2 + zi2;
+    const bool esc = mag > T(4);
+    const uint64_t e = __builtin_amdgcn_ballot_w64(esc) & live;
+    if (__builtin_expect(e != 0, 0)) {
+      asm volatile("" ::: "memory");  // keep this rare path a branch, not selects
+      if (esc && n == max_iter) n = it;
+      live &= ~e;
+    }
+    T t = zr * zi;
+    T tt = t + t;
+    zi = tt + ci;
+    T d = zr2 - zi2;
+    zr = d + cr;
+    ++it;
+  } while (it < max_iter && live != 0);
+  return n;
+}
+
+template <typename T>
+__device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
+  T re_min, im_min, step_re, step_im;
+  if constexpr (sizeof(T) == 8) {
+    re_min = d.p.m64.re_min;
+    im_min = d.p.m64.im_min;
+    step_re = d.p.m64.step_re;
+    step_im = d.p.m64.step_im;
+  } else {
+    re_min = d.p.m32.re_min;  // rounded to float once by the host
+    im_min = d.p.m32.im_min;
+    step_re = d.p.m32.step_re;
+    step_im = d.p.m32.step_im;
+  }
+  const uint32_t width = d.p.m64.width, row0 = d.p.m64.row0, rows = d.p.m64.rows;
+  const uint32_t max_iter = d.p.m64.max_iter;
+  uint16_t* out = reinterpret_cast<uint16_t*>(d.out);
+  const uint32_t bw = (width + kMandelBlockW - 1) / kMandelBlockW;
+  const uint32_t nb = mandel_blocks(width, rows);
+  const uint32_t bpt = d.tcfg / 64;
+  const uint32_t b0 = tile * bpt;
+  const uint32_t b1 = min(nb, b0 + bpt);
+  const uint32_t lane = lane_id();
+  if (threadIdx.x == 0) *lds_ctr = 0;
+  __syncthreads();
+  for (;;) {
+    uint32_t b = 0;
+    if (lane == 0) b = atomicAdd(lds_ctr, 1u);
+    b = __builtin_amdgcn_readfirstlane(b) + b0;
+    if (b >= b1) break;
+    const uint32_t by = b / bw, bx = b - by * bw;
+    const uint32_t y = by * kMandelBlockH + lane / kMandelBlockW;
+    const uint32_t x = bx * kMandelBlockW + lane % kMandelBlockW;
+    const bool valid = y < rows && x < width;
+    T gx = (T)x;
+    T xm = gx * step_re;
+    T cr = re_min + xm;
+    T gy = (T)(row0 + y);
+    T ym = gy * step_im;
+    T ci = im_min + ym;
+    const uint32_t n = escape_count<T>(cr, ci, max_iter, valid);
+    if (valid) out[(uint64_t)y * width + x] = (uint16_t)n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense product C = A * B of flat row-major n x n matrices (Sec. 4.6, the
+// matrix_multiply actor: two input arrays, the output array last), on the
+// matrix cores with fp32 accumulation.  A work tile is a TE x TE block of C
+// (TE = 64 or 128); its four waves each own a (TE/2) x (TE/2) quarter made
+// of 32 x 32 MFMA blocks.  K advances in LDS-staged slices; rows, columns
+// and k beyond n are zero-filled on load and masked on store, so any n
+// works.
+//
+// MFMA operand layout used (32 x 32 output blocks): lane l supplies A row
+// l % 32 and B column l % 32; the k index a lane supplies is the same
+// function of (l / 32, element) for A and B, so the product sums every k
+// exactly once.  Output register r of lane l holds row
+// 8*(r/4) + 4*(l/32) + r%4, column l % 32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tile_coords(uint32_t tile, uint32_t n, uint32_t te,
+                                            uint32_t& tm, uint32_t& tn) {
+  const uint32_t tpr = (n + te - 1) / te;
+  tm = tile / tpr;
+  tn = tile - tm * tpr;
+}
+
+template <int TE>
+__device__ __forceinline__ void store_c(float* C, uint32_t n, uint32_t row_base,
+                                        uint32_t col_base, const floatx16& acc) {
+  const uint32_t lane = lane_id();
+  const uint32_t col = col_base + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint32_t row = row_base + 8 * (r / 4) + 4 * (lane >> 5) + (r & 3);
+    if (row < n && col < n) C[(uint64_t)row * n + col] = acc[r];
+  }
+}
+
+// fp32 inputs: v_mfma_f32_32x32x2f32, k slices of 16.
+template <int TE>
+__device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restrict__ B,
+                              float* __restrict__ C, uint32_t n, uint32_t tile, float* smem) {
+  constexpr int BK = 16;
+  constexpr int WB = TE / 64;  // 32x32 blocks per wave and dimension
+  float* As = smem;            // [BK][TE], k-major (transposed)
+  float* Bs = smem + BK * TE;  // [BK][TE], row-major
+  uint32_t tm, tn;
+  tile_coords(tile, n, TE, tm, tn);
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const uint32_t wm = w >> 1, wn = w & 1;
+  const bool vec = (n % 4u) == 0 && ((reinterpret_cast<uintptr_t>(A) |
+                                      reinterpret_cast<uintptr_t>(B)) & 15u) == 0;
+  floatx16 acc[WB][WB];
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < TE * BK / 4 / kThreads; ++q) {
+        const uint32_t idx = t + kThreads * q;
+        // A: row idx/4, k quad idx%4
+        {
+          const uint32_t row = idx >> 2, kq = (idx & 3) * 4;
+          const uint32_t gr = tm * TE + row, gk = k0 + kq;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (gr < n && gk < n) v = *reinterpret_cast<const float4*>(A + (uint64_t)gr * n + gk);
+          As[(kq + 0) * TE + row] = v.x;
+          As[(kq + 1) * TE + row] = v.y;
+          As[(kq + 2) * TE + row] = v.z;
+          As[(kq + 3) * TE + row] = v.w;
+        }
+        // B: k row idx/(TE/4), column quad
+        {
+          const uint32_t kr = idx / (TE / 4), c = (idx % (TE / 4)) * 4;
+          const uint32_t gk = k0 + kr, gc = tn * TE + c;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (gk < n && gc < n) v = *reinterpret_cast<const float4*>(B + (uint64_t)gk * n + gc);
+          *reinterpret_cast<float4*>(Bs + kr * TE + c) = v;
+        }
+      }
+    } else {
+      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
+        const uint32_t row = idx / BK, kk = idx % BK;
+        const uint32_t gr = tm * TE + row, gk = k0 + kk;
+        As[kk * TE + row] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : 0.f;
+        const uint32_t kr = idx / TE, c = idx % TE;
+        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+        Bs[kr * TE + c] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const uint32_t kr = kk + (lane >> 5);
+      float a[WB], b[WB];
+#pragma unroll
+      for (int i = 0; i < WB; ++i) a[i] = As[kr * TE + wm * (TE / 2) + i * 32 + (lane & 31)];
+#pragma unroll
+      for (int j = 0; j < WB; ++j) b[j] = Bs[kr * TE + wn * (TE / 2) + j * 32 + (lane & 31)];
+#pragma unroll
+      for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int j = 0; j < WB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+      store_c<TE>(C, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
+                  acc[i][j]);
+}
+
+// bfloat16 inputs: v_mfma_f32_32x32x16_bf16, k slices of 32.  Both operands
+// are kept k-contiguous in LDS ([row][k] for A, [column][k] for B, rows
+// padded to 80 bytes) so each lane reads its 8 k values with one 16-byte
+// LDS load.
+template <int TE>
+__device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+                               float* __restrict__ C, uint32_t n, uint32_t tile,
+                               uint16_t* smem) {
+  constexpr int BK = 32;
+  constexpr int LD = BK + 8;
+  constexpr int WB = TE / 64;
+  uint16_t* As = smem;            // [TE][LD]
+  uint16_t* Bs = smem + TE * LD;  // [TE][LD] (transposed B)
+  uint32_t tm, tn;
+  tile_coords(tile, n, TE, tm, tn);
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const uint32_t wm = w >> 1, wn = w & 1;
+  const bool vec = (n % 8u) == 0 && ((reinterpret_cast<uintptr_t>(A) |
+                                      reinterpret_cast<uintptr_t>(B)) & 15u) == 0;
+  floatx16 acc[WB][WB];
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < TE * BK / 8 / kThreads; ++q) {
+        const uint32_t idx = t + kThreads * q;
+        {  // A chunk: row idx/4, 8 k values
+          const uint32_t row = idx >> 2, kc = (idx & 3) * 8;
+          const uint32_t gr = tm * TE + row, gk = k0 + kc;
+          uint4 v = make_uint4(0, 0, 0, 0);
+          if (gr < n && gk < n) v = *reinterpret_cast<const uint4*>(A + (uint64_t)gr * n + gk);
+          *reinterpret_cast<uint4*>(As + row * LD + kc) = v;
+        }
+        {  // B chunk: k row idx/(TE/8), 8 columns -> transposed store
+          const uint32_t kr = idx / (TE / 8), c = (idx % (TE / 8)) * 8;
+          const uint32_t gk = k0 + kr, gc = tn * TE + c;
+          uint4 v = make_uint4(0, 0, 0, 0);
+          if (gk < n && gc < n) v = *reinterpret_cast<const uint4*>(B + (uint64_t)gk * n + gc);
+          const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q2 = 0; q2 < 4; ++q2) {
+            Bs[(c + 2 * q2) * LD + kr] = (uint16_t)(e[q2] & 0xFFFFu);
+            Bs[(c + 2 * q2 + 1) * LD + kr] = (uint16_t)(e[q2] >> 16);
+          }
+        }
+      }
+    } else {
+      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
+        const uint32_t row = idx / BK, kk = idx % BK;
+        const uint32_t gr = tm * TE + row, gk = k0 + kk;
+        As[row * LD + kk] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : (uint16_t)0;
+        const uint32_t kr = idx / TE, c = idx % TE;
+        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+        Bs[c * LD + kr] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : (uint16_t)0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const uint32_t kc = ks + 8 * (lane >> 5);
+      bf16x8 a[WB], b[WB];
+#pragma unroll
+      for (int i = 0; i < WB; ++i)
+        a[i] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(
+                        As + (wm * (TE / 2) + i * 32 + (lane & 31)) * LD + kc));
+#pragma unroll
+      for (int j = 0; j < WB; ++j)
+        b[j] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(
+                        Bs + (wn * (TE / 2) + j * 32 + (lane & 31)) * LD + kc));
+#pragma unroll
+      for (int i = 0; i < WB; ++i)
+#pragma unroll
+        for (int j = 0; j < WB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j)
+      store_c<TE>(C, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
+                  acc[i][j]);
+}
+
+// ---------------------------------------------------------------------------
+// Support behaviours (pipeline stages and ping-pong).
+// ---------------------------------------------------------------------------
+__device__ void tanh_tile(const float* __restrict__ x, float* __restrict__ y, uint64_t count,
+                          uint32_t tile) {
+  const uint64_t base = (uint64_t)tile * kTanhTile;
+#pragma unroll 4
+  for (uint32_t e = threadIdx.x; e < kTanhTile; e += kThreads) {
+    const uint64_t i = base + e;
+    if (i < count) y[i] = tanhf(x[i]);
+  }
+}
+
+__device__ void rowsum_tile(const float* __restrict__ x, float* __restrict__ y, uint32_t rows,
+                            uint32_t cols, uint32_t tile) {
+  const uint32_t lane = lane_id(), w = wave_id();
+  for (uint32_t rr = w; rr < kRowsumTile; rr += 4) {
+    const uint32_t r = tile * kRowsumTile + rr;
+    if (r >= rows) break;
+    const float* row = x + (uint64_t)r * cols;
+    float s = 0.f;
+    for (uint32_t c = lane; c < cols; c += 64) s += row[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) y[r] = s;
+  }
+}
+
+__device__ void echo_tile(const Desc& d, uint8_t* inline_out) {
+  const uint32_t n = d.numel;
+  int32_t* dst = (d.flags & DF_INLINE_OUT) ? reinterpret_cast<int32_t*>(inline_out)
+                                           : reinterpret_cast<int32_t*>(d.out);
+  if (d.flags & DF_INLINE_IN) {
+    // at most four values travel in the parameter block
+    uint32_t w[4];
+    __builtin_memcpy(w, d.p.raw, sizeof w);
+    const uint32_t i = threadIdx.x;
+    if (i < n) dst[i] = (int32_t)(i == 0 ? w[0] : i == 1 ? w[1] : i == 2 ? w[2] : w[3]);
+    return;
+  }
+  const int32_t* src = reinterpret_cast<const int32_t*>(d.in0);
+  for (uint32_t i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+}
+
+}  // namespace cafgpu

@@ -19,3 +19,11 @@ def gpu_available() -> bool:
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+@pytest.fixture(autouse=True)
+def _name_the_case(request):
+    # Printed and flushed before each case, so a crash names what ran.
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[case] {request.node.nodeid}", flush=True)
+    yield

@@ -1,0 +1,166 @@
+"""Parity of the HIP compute actors with the CPU oracle (GPU).
+
+Mandelbrot counts must be bit-exact in float and double; GEMM must be within
+1e-5 (fp32 inputs) / 2e-2 (bf16 inputs) relative Frobenius error of the
+float64 oracle.  Every case runs through the C ABI in each of the three
+delivery modes (one launch per message, batched drain, persistent drain).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_07368_amd import gen
+from tests.gpu_util import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["plain", "batched", "persistent"]
+
+
+@pytest.fixture(scope="module", params=MODES)
+def sysm(request):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    assert torch.cuda.is_available()
+    s = cg.System(mode=request.param, arena_bytes=512 << 20, idle_exit_us=50000)
+    yield s
+    s.shutdown()
+
+
+def _mandel(s, vp, row0, rows, fp):
+    from paper_1505_07368_amd import binding as cg
+    a = s.spawn(cg.BHV_MANDELBROT)
+    st, img = s.request(a, cg.mandel_args(vp, row0=row0, rows=rows, fp=fp)).result()
+    assert st == cg.OK, st
+    return img.cpu().numpy().reshape(rows, vp.width)
+
+
+@pytest.mark.parametrize("fp", ["f32", "f64"])
+def test_tiny_viewport_bit_exact(sysm, fp):
+    from paper_1505_07368_amd import binding as cg
+    vp = gen.tiny_viewport()
+    code = cg.F32 if fp == "f32" else cg.F64
+    got = _mandel(sysm, vp, 0, 512, code)
+    ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 512, 0, 512, 100, fp)
+    assert (got == ref).all(), int((got != ref).sum())
+
+
+@pytest.mark.parametrize("fp", ["f32", "f64"])
+def test_hand_orbit_points(sysm, fp):
+    """1x1 requests whose corner is the point c."""
+    from paper_1505_07368_amd import binding as cg
+    from paper_1505_07368_amd.gen import Viewport
+    code = cg.F32 if fp == "f32" else cg.F64
+    for c, expect in [(0j, None), (-2 + 0j, None), (0.25 + 0j, None), (1j, None),
+                      (1 + 0j, 3), (2j, 2), (0.5 + 0j, 5), (-2.5 + 0j, 1)]:
+        vp = Viewport(c.real, c.imag, 0.0, 0.0, 1, 1, 1000)
+        got = int(_mandel(sysm, vp, 0, 1, code)[0, 0])
+        assert got == (1000 if expect is None else expect), (c, got)
+
+
+@pytest.mark.parametrize("fp", ["f32", "f64"])
+def test_ragged_tiles_and_edges(sysm, fp):
+    """Widths and row counts that are not multiples of the 4x16 pixel block
+    or of the work tile, tiles starting at odd rows, and an empty tile."""
+    from paper_1505_07368_amd import binding as cg
+    code = cg.F32 if fp == "f32" else cg.F64
+    vp = gen.boundary_viewport(5, width=203, height=77, max_iter=400)
+    whole = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 203, 0, 77, 400, fp)
+    for r0, rows in [(0, 77), (3, 1), (13, 29), (76, 1), (10, 0)]:
+        got = _mandel(sysm, vp, r0, rows, code)
+        assert got.shape == (rows, 203)
+        assert (got == whole[r0:r0 + rows]).all(), (r0, rows)
+
+
+def test_full_image_tiles_sampled_rows(sysm):
+    """1920x1080 at max_iter 1000 in 17 tile messages of 64 rows (the last
+    has 56); sampled rows checked bit-exact against the oracle."""
+    from paper_1505_07368_amd import binding as cg
+    vp = gen.boundary_viewport(1)
+    a = sysm.spawn(cg.BHV_MANDELBROT)
+    tiles = gen.row_tiles(1080, 64)
+    assert len(tiles) == 17 and tiles[-1] == (1024, 56)
+    futs = [(r0, rows, sysm.request(a, cg.mandel_args(vp, row0=r0, rows=rows)))
+            for r0, rows in tiles]
+    img = np.zeros((1080, 1920), np.uint16)
+    for r0, rows, f in futs:
+        st, t = f.result()
+        assert st == cg.OK
+        img[r0:r0 + rows] = t.cpu().numpy().reshape(rows, 1920)
+    g = gen.rng(77)
+    for y in sorted(set(g.integers(0, 1080, size=6).tolist()) | {0, 1023, 1024, 1079}):
+        ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 1920, y, 1, 1000)
+        assert (img[y] == ref[0]).all(), y
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 31, 33, 64, 100, 128, 130, 256])
+def test_gemm_f32(sysm, n):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    g = sysm.spawn(cg.BHV_GEMM)
+    A, B = gen.gemm_pair(n, n)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    st, C = sysm.request(g, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt]).result()
+    assert st == cg.OK
+    err = rel_fro(C.cpu().numpy().reshape(n, n), oracle.gemm(A, B))
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("n", [1, 7, 8, 33, 64, 128, 256])
+def test_gemm_bf16(sysm, n):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    g = sysm.spawn(cg.BHV_GEMM)
+    A, B = gen.gemm_pair(n + 1, n, "bf16")
+    At = torch.from_numpy(A.view(np.int16)).cuda().view(torch.bfloat16)
+    Bt = torch.from_numpy(B.view(np.int16)).cuda().view(torch.bfloat16)
+    torch.cuda.synchronize()
+    st, C = sysm.request(g, cg.caf_gemm_args(n, cg.BF16), inputs=[At, Bt]).result()
+    assert st == cg.OK
+    err = rel_fro(C.cpu().numpy().reshape(n, n), oracle.gemm(A, B, "bf16"))
+    assert err <= 2e-2, err
+    # against the widened bf16 inputs the product is fp32-accurate
+    assert err <= 1e-5, err
+
+
+def test_gemm_integer_exact(sysm):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    g = sysm.spawn(cg.BHV_GEMM)
+    n = 96
+    A, B = gen.integer_matrix(1, n), gen.integer_matrix(2, n)
+    ref = A.astype(np.int64) @ B.astype(np.int64)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    st, C = sysm.request(g, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt]).result()
+    assert st == cg.OK and (C.cpu().numpy().reshape(n, n) == ref).all()
+    Ab = torch.from_numpy(gen.to_bf16_bits(A).view(np.int16)).cuda().view(torch.bfloat16)
+    Bb = torch.from_numpy(gen.to_bf16_bits(B).view(np.int16)).cuda().view(torch.bfloat16)
+    torch.cuda.synchronize()
+    st, C = sysm.request(g, cg.caf_gemm_args(n, cg.BF16), inputs=[Ab, Bb]).result()
+    assert st == cg.OK and (C.cpu().numpy().reshape(n, n) == ref).all()
+
+
+def test_echo_and_pipeline(sysm):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    e = sysm.spawn(cg.BHV_NOOP)
+    st, v = sysm.request(e, inputs=[np.array([1, 2, 3], np.int32)]).result()
+    assert st == cg.OK and v.tolist() == [1, 2, 3]
+    big = torch.arange(1000, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    st, v = sysm.request(e, inputs=[big]).result()
+    assert st == cg.OK and (v.cpu() == big.cpu()).all()
+    n = 128
+    rs = sysm.spawn(cg.BHV_ROWSUM, n=n)
+    th = sysm.spawn(cg.BHV_TANH, n=n, forward_to=rs)
+    gm = sysm.spawn(cg.BHV_GEMM, n=n)
+    A, B = gen.gemm_pair(42, n)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    st, y = sysm.request(gm, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt],
+                         forward_to=th).result()
+    assert st == cg.OK
+    err = rel_fro(y.cpu().numpy(), oracle.chain(A, B))
+    assert err <= 1e-5, err
