@@ -32,6 +32,9 @@ def _mandel(s, vp, row0, rows, fp):
     a = s.spawn(cg.BHV_MANDELBROT)
     st, img = s.request(a, cg.mandel_args(vp, row0=row0, rows=rows, fp=fp)).result()
     assert st == cg.OK, st
+    if rows == 0:
+        assert img is None  # an empty tile replies with an empty buffer
+        return np.zeros((0, vp.width), np.uint16)
     return img.cpu().numpy().reshape(rows, vp.width)
 
 
