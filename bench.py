@@ -1,0 +1,251 @@
+"""Benchmark of the compute-actor hot path on one MI355X.
+
+Workload (the headline): Mandelbrot 1920x1080 at max_iter 1000, eight
+seeded viewports on the main cardioid's boundary (zoom 1 to 1e4), each image
+split into 17 row-tile messages of 64 rows (the last 56) sent to one GPU
+actor.  One step = all 8 x 17 = 136 tile requests through the C ABI,
+issued by the native driver and waited for.  `value` is Mandelbrot Giter/s
+(sum of the exact escape counts of the replies per second) of the batched
+mailbox-drain form in float; the same step in double, the persistent form
+and the one-launch-per-message form are reported beside it, with reply
+latency percentiles, plus the small-message comparison (int32 echo
+ping-pong, 64x64 tiles, n = 64 GEMMs) of the three forms.
+
+Prints ONE JSON line.  Only --gpus 1 is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: unpacked fp32/fp64 ops/s
+OPS_PER_ITER = 9                      # 3 mul + 5 add/sub + 1 compare per escape-time iteration
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def image_messages(cg, actor, seeds, fp):
+    from paper_1505_07368_amd import gen
+    msgs = []
+    for seed in seeds:
+        vp = gen.boundary_viewport(seed)
+        for r0, rows in gen.row_tiles(vp.height, 64):
+            msgs.append({"actor": actor, "args": cg.mandel_args(vp, row0=r0, rows=rows, fp=fp)})
+    return msgs
+
+
+def percentiles(lat_ns):
+    lat = np.asarray(lat_ns, np.float64)
+    lat = lat[lat >= 0] / 1e3
+    if lat.size == 0:
+        return None, None
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False):
+    """Runs the image workload in one delivery mode; returns a dict."""
+    s = cg.System(mode=mode, arena_bytes=1 << 30, ring_slots=4096, idle_exit_us=200000)
+    try:
+        a = s.spawn(cg.BHV_MANDELBROT)
+        msgs = image_messages(cg, a, seeds, fp)
+        # exact algorithmic work of one step: the sum of the reply counts
+        outs = []
+        for m in msgs:
+            args = m["args"]
+            outs.append(torch.empty(args.rows * args.width, dtype=torch.uint16, device="cuda"))
+        chk = [dict(m, out=o) for m, o in zip(msgs, outs)]
+        torch.cuda.synchronize()
+        rc, _, st, _ = s.drive(chk, window=len(chk))
+        assert rc == cg.OK and (st == cg.OK).all(), (rc, st)
+        iters = int(sum(int(o.to(torch.int64).sum()) for o in outs))
+        for _ in range(warmup):
+            s.drive(msgs, window=len(msgs))
+        s.drain_kernel_ms()  # reset the launch timers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lats = []
+        for _ in range(steps):
+            rc, lat, st, _ = s.drive(msgs, window=len(msgs))
+            assert rc == cg.OK and (st == cg.OK).all()
+            lats.append(lat)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kms, launches = s.drain_kernel_ms()
+        p50, p99 = percentiles(np.concatenate(lats))
+        out = {"giter_s": iters * steps / dt / 1e9, "msgs_per_s": len(msgs) * steps / dt,
+               "ms_per_step": dt / steps * 1e3, "iters_per_step": iters,
+               "p50_us": p50, "p99_us": p99, "messages_per_step": len(msgs)}
+        if timed_kernel and launches:
+            out["kernel_ms_total"] = kms
+            out["kernel_launches"] = launches
+        return out
+    finally:
+        s.shutdown()
+
+
+def small_leg(cg, torch, mode, kind, count, window):
+    """Small messages through one form: echo (int32), 64x64 Mandelbrot tile,
+    or n = 64 fp32 GEMM.  Returns msgs/s and latency percentiles."""
+    from paper_1505_07368_amd import gen
+    s = cg.System(mode=mode, arena_bytes=256 << 20, ring_slots=4096, idle_exit_us=200000)
+    try:
+        keep = []
+        if kind == "echo":
+            a = s.spawn(cg.BHV_NOOP)
+            x = np.array([42], np.int32)
+            keep.append(x)
+            msgs = [{"actor": a, "inputs": [x]} for _ in range(count)]
+        elif kind == "mandel64":
+            a = s.spawn(cg.BHV_MANDELBROT)
+            vp = gen.tiny_viewport()
+            msgs = [{"actor": a, "args": cg.caf_mandel_args(
+                vp.re_min + 64 * vp.step_re * (i % 8), vp.im_min, vp.step_re, vp.step_im,
+                64, 512, 64 * ((i // 8) % 8), 64, 100, cg.F32)} for i in range(count)]
+        else:
+            a = s.spawn(cg.BHV_GEMM)
+            A, B = gen.gemm_pair(3, 64)
+            At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            keep += [At, Bt]
+            msgs = [{"actor": a, "args": cg.caf_gemm_args(64, cg.F32), "inputs": [At, Bt]}
+                    for _ in range(count)]
+        torch.cuda.synchronize()
+        s.drive(msgs[: min(len(msgs), 256)], window=window)  # warm-up
+        rc, lat, st, el = s.drive(msgs, window=window)
+        assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+        p50, p99 = percentiles(lat)
+        return {"msgs_per_s": count / el, "p50_us": p50, "p99_us": p99}
+    finally:
+        s.shutdown()
+
+
+def cpu_oracle_tile(args):
+    import oracle
+    vp, r0, rows = args
+    t = time.perf_counter()
+    img = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, r0, rows,
+                            vp.max_iter, "f32")
+    return int(img.sum(dtype=np.int64)), time.perf_counter() - t
+
+
+def cpu_baseline(seeds=(0, 1), cores=16):
+    """The oracle, as it stands, on the host's cores: independent
+    single-threaded instances over disjoint tile messages."""
+    import multiprocessing as mp
+    from paper_1505_07368_amd import gen
+    import oracle
+    oracle.lib()  # built before forking
+    work = []
+    for seed in seeds:
+        vp = gen.boundary_viewport(seed)
+        work += [(vp, r0, rows) for r0, rows in gen.row_tiles(vp.height, 64)]
+    cores = max(1, min(cores, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(cpu_oracle_tile, work, chunksize=1)
+    dt = time.perf_counter() - t0
+    iters = sum(r[0] for r in res)
+    return {"value": iters / dt / 1e9, "unit": "Giter/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(work)} tile messages ({len(seeds)} images 1920x1080, max_iter "
+                      f"1000, fp32), {iters / 1e9:.2f} Giter in {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--quick", action="store_true", help="headline leg only")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the compute-actor path runs on a single MI355X; "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    seeds = list(range(8))
+
+    log("[bench] batched fp32 (headline)")
+    head = mandel_leg(cg, torch, "batched", cg.F32, args.steps, args.warmup, seeds, True)
+    result = {
+        "metric": "GPU-actor msgs/s + Mandelbrot Giter/s; p50/p99 reply latency vs 1-launch/msg",
+        "value": round(head["giter_s"], 2),
+        "unit": "Giter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mandelbrot 1920x1080 max_iter 1000, 8 seeded boundary "
+                               "viewports x 17 row-tile messages (64 rows, last 56), fp32, "
+                               "batched mailbox drain",
+                   "images": len(seeds), "tile_rows": 64, "max_iter": 1000,
+                   "messages_per_step": head["messages_per_step"],
+                   "iters_per_step": head["iters_per_step"]},
+        "msgs_per_s": round(head["msgs_per_s"], 1),
+        "p50_us": head["p50_us"],
+        "p99_us": head["p99_us"],
+    }
+    kms = head.get("kernel_ms_total")
+    if kms:
+        per_launch_ms = kms / head["kernel_launches"]
+        ops = head["iters_per_step"] * args.steps * OPS_PER_ITER
+        achieved = ops / (kms * 1e-3)
+        result["roofline"] = {
+            "bound": "alu", "achieved": round(achieved / 1e12, 3),
+            "peak": round(VALU_LANE_OPS / 1e12, 3), "unit": "TFLOP/s",
+            "frac": round(achieved / VALU_LANE_OPS, 4), "traffic": None,
+            "kernel": "drain_kernel", "launches": head["kernel_launches"],
+            "avg_launch_ms": round(per_launch_ms, 4)}
+    if not args.quick:
+        log("[bench] batched fp64")
+        f64 = mandel_leg(cg, torch, "batched", cg.F64, max(2, args.steps // 2), 1, seeds, True)
+        result["fp64"] = {k: f64[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us",
+                                              "iters_per_step")}
+        if f64.get("kernel_ms_total"):
+            result["fp64"]["alu_frac"] = round(
+                f64["iters_per_step"] * max(2, args.steps // 2) * OPS_PER_ITER
+                / (f64["kernel_ms_total"] * 1e-3) / VALU_LANE_OPS, 4)
+        for mode in ("persistent", "plain"):
+            log(f"[bench] {mode} fp32")
+            r = mandel_leg(cg, torch, mode, cg.F32, max(2, args.steps // 2), 1, seeds)
+            result[mode] = {k: r[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
+        small = {}
+        for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096)):
+            for window in ((1, 64, 1024) if kind == "echo" else (256,)):
+                row = {}
+                for mode in ("plain", "batched", "persistent"):
+                    log(f"[bench] small {kind} window {window} {mode}")
+                    row[mode] = small_leg(cg, torch, mode, kind, count, window)
+                row["persistent_over_plain"] = round(
+                    row["persistent"]["msgs_per_s"] / row["plain"]["msgs_per_s"], 2)
+                row["batched_over_plain"] = round(
+                    row["batched"]["msgs_per_s"] / row["plain"]["msgs_per_s"], 2)
+                small[f"{kind}_w{window}"] = row
+        result["small_messages"] = small
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

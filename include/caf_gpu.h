@@ -121,9 +121,11 @@ typedef struct {
   uint32_t max_batch;    /* messages drained per pass (the paper's max_msgs, Sec. 6); 0 = 1024 */
   uint32_t grid;         /* drain-kernel workgroups; 0 = chosen from occupancy */
   uint32_t blocking;     /* 1: requests wait for budget/mailbox space; 0: CAF_E_OVERLOAD */
-  uint32_t idle_exit_us; /* persistent kernel: exit after this long without work; 0 = 200000 */
+  uint32_t idle_exit_us; /* drain kernel exits after this long without work;
+                            0 = 200000 (persistent), 50 (batched) */
   int32_t grouping;      /* caf_grouping */
-  uint32_t mandel_tile_px; /* pixels per Mandelbrot work tile (multiple of 256); 0 = 1024 */
+  uint32_t mandel_tile_px; /* pixels per Mandelbrot work tile (multiple of 256);
+                              0 = 512 (plain), 1024 (batched / persistent) */
   uint32_t gemm_tile;      /* GEMM output tile edge (64 or 128); 0 = by n */
 } caf_gpu_config;
 

@@ -81,31 +81,34 @@ struct alignas(64) HostCtl {
   uint8_t pad0[56];
   uint64_t drained;   // mailbox entries copied to the device (device writes)
   uint8_t pad1[56];
-  uint32_t stop;      // host asks the drain kernel to exit
-  uint32_t exited_gen;  // generation of the last drain launch that fully exited
-  uint8_t pad2[56];
+  uint32_t stop;         // host asks the drain kernel to exit
+  uint32_t exited[2];    // by launch parity: generation whose workgroups all exited
+  uint32_t retiring[2];  // by launch parity: generation that began to retire
+  uint8_t pad2[44];
   uint32_t alive[kAliveWords];  // bit per actor
 };
 
-// Device-resident control block (agent-scope atomics only).
-struct alignas(64) DevCtl {
-  uint64_t drained;
-  uint8_t p0[56];
+// Device-resident control block (agent-scope atomics only).  The hot
+// counters sit on separate 128-byte lines (the L2 line size).
+struct alignas(128) DevCtl {
+  uint64_t tiles_claimed;  // reservation cursor (fetch_add)
+  uint8_t p0[120];
   uint64_t tiles_pub;      // work tiles published (claimable below this)
-  uint8_t p1[56];
-  uint64_t tiles_claimed;  // claim cursor
-  uint8_t p2[56];
-  uint64_t tiles_done;
-  uint8_t p3[56];
+  uint8_t p1[120];
+  uint64_t tiles_done;     // tiles finished (flow control of the tile map)
+  uint8_t p2[120];
   uint32_t drain_lock;
-  uint8_t p4[60];
-  uint32_t wg_exited;
-  uint8_t p5[60];
+  uint8_t p3[124];
   uint64_t comp_tail;      // completion positions handed out
-  uint8_t p6[56];
+  uint8_t p4[120];
+  uint64_t drained;        // mailbox entries drained
   uint32_t stop_seen;      // a drainer saw the host's stop flag
-  uint8_t p7[60];
+  uint32_t wg_exited[2];   // by launch parity: workgroups that left
+  uint32_t retiring[2];    // by launch parity: generation that began to retire
+  uint8_t p5[100];
 };
+
+constexpr uint32_t kNopTile = 0xFFFFFFFFu;  // tile-map entry of a filler tile
 
 struct alignas(16) DevSlot {
   Desc d;              // the message currently held by this slot
@@ -145,6 +148,7 @@ struct KArgs {
   uint32_t exit_on_empty; // batched mode
   uint32_t grouping;
   uint32_t grid;
+  uint32_t full;          // drain launch variant: 1 = every behaviour, 0 = all but GEMM
 };
 
 // ---- work-tile geometry (host and device agree on it) -------------------
@@ -179,4 +183,23 @@ __host__ __device__ inline uint32_t desc_ntiles(const Desc& d) {
   }
 }
 
+// Completion notifications for one native driver: the poller thread pushes
+// the tag of each resolved tagged future, the driver pops (single producer,
+// single consumer).
+struct DriveQ {
+  uint32_t* buf = nullptr;
+  uint64_t mask = 0;
+  alignas(64) uint64_t head = 0;  // consumer
+  alignas(64) uint64_t tail = 0;  // producer
+};
+
 }  // namespace cafgpu
+
+// Request entry used by the native driver: like caf_gpu_request, and the
+// poller pushes `tag` into `q` when the future resolves.
+int cafgpu_request_tagged(caf_gpu_system* sys, caf_actor dst, uint32_t sender, const void* args,
+                          uint64_t args_bytes, const caf_buf* in, uint32_t n_in,
+                          const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut,
+                          cafgpu::DriveQ* q, uint32_t tag);
+int64_t cafgpu_future_issue_ns(const caf_future* f);
+int64_t cafgpu_future_done_ns(const caf_future* f);

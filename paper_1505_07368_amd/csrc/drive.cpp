@@ -1,6 +1,6 @@
-// Native load driver: issues a list of requests through the public C ABI
-// and records per-request reply latency, so benchmarks measure the actor
-// runtime rather than Python call overhead.
+// Native load driver: issues a list of requests through the library's
+// request path and records per-request reply latency, so benchmarks measure
+// the actor runtime rather than Python call overhead.
 //
 //  * closed loop: at most `window` requests outstanding (window 1 is
 //    ping-pong); latency = reply time - issue time.
@@ -9,6 +9,10 @@
 //    (no coordinated omission).
 //  * host-mediated chains: each reply is re-sent by the host to the next
 //    pipeline actor, the comparison point for device-side forwarding.
+//
+// Replies are harvested through a completion queue that the poller thread
+// fills with the tags of resolved requests, so harvesting costs O(1) per
+// reply whatever the window.
 #include <immintrin.h>
 
 #include <chrono>
@@ -16,10 +20,7 @@
 #include <cstring>
 #include <vector>
 
-#include "../../include/caf_gpu.h"
-
-int64_t cafgpu_future_issue_ns(const caf_future* f);
-int64_t cafgpu_future_done_ns(const caf_future* f);
+#include "caf_internal.h"
 
 namespace {
 
@@ -52,34 +53,49 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
     if (latency_ns) latency_ns[i] = -1;
     if (status) status[i] = CAF_E_INVALID;
   }
-  std::vector<Pending> pend;
-  pend.reserve(window + 8);
+  uint64_t qcap = 64;
+  while (qcap < 2ull * window + 64) qcap <<= 1;
+  std::vector<uint32_t> qbuf(qcap);
+  cafgpu::DriveQ q;
+  q.buf = qbuf.data();
+  q.mask = qcap - 1;
+  std::vector<Pending> pend(window);
+  std::vector<uint32_t> free_tags;
+  free_tags.reserve(window);
+  for (uint32_t k = 0; k < window; ++k) free_tags.push_back(window - 1 - k);
   int first_err = CAF_OK;
-  const int64_t t_start = now_ns();
   uint64_t next = 0, done = 0;
+  const int64_t t_start = now_ns();
 
-  auto issue_first = [&](uint64_t i, int64_t t_ref) -> bool {
-    const caf_msg& m = msgs[i];
-    const bool final_here = chain_hops == 0;
-    caf_future* f = nullptr;
-    int st = caf_gpu_request(sys, m.actor, m.sender, m.args, m.args_bytes, m.in, m.n_in,
-                             (final_here && m.out.data) ? &m.out : nullptr, m.forward_to, &f);
-    if (st != CAF_OK) {
-      if (status) status[i] = st;
-      if (st != CAF_E_OVERLOAD && first_err == CAF_OK) first_err = st;
-      ++done;
-      return false;
-    }
-    Pending p;
-    p.f = f;
-    p.idx = i;
-    p.t_ref = t_ref;
-    pend.push_back(p);
-    return true;
+  auto fail = [&](uint64_t i, int st) {
+    if (status) status[i] = st;
+    if (st != CAF_E_OVERLOAD && first_err == CAF_OK) first_err = st;
+    ++done;
   };
 
-  // Handles a resolved entry; returns true if it stays pending (next stage).
-  auto on_reply = [&](Pending& p) -> bool {
+  auto issue_first = [&](uint64_t i, int64_t t_sched) {
+    const caf_msg& m = msgs[i];
+    const uint32_t tag = free_tags.back();
+    caf_future* f = nullptr;
+    const bool final_here = chain_hops == 0;
+    const int st = cafgpu_request_tagged(sys, m.actor, m.sender, m.args, m.args_bytes, m.in,
+                                         m.n_in, (final_here && m.out.data) ? &m.out : nullptr,
+                                         m.forward_to, &f, &q, tag);
+    if (st != CAF_OK) {
+      fail(i, st);
+      return;
+    }
+    free_tags.pop_back();
+    Pending& p = pend[tag];
+    p = Pending();
+    p.f = f;
+    p.idx = i;
+    p.t_ref = t_sched >= 0 ? t_sched : cafgpu_future_issue_ns(f);
+  };
+
+  // Handles the resolved request of tag k.
+  auto on_reply = [&](uint32_t k) {
+    Pending& p = pend[k];
     caf_buf res{};
     int32_t rs = CAF_OK;
     caf_future_poll(p.f, &res, &rs);
@@ -90,76 +106,63 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
     if (rs == CAF_OK && p.stage < chain_hops) {
       const caf_msg& m = msgs[p.idx];
       const uint32_t n = (uint32_t)std::llround(std::sqrt((double)res.numel));
-      Pending q;
-      q.prev = p.f;
-      q.idx = p.idx;
-      q.stage = p.stage + 1;
-      q.t_ref = p.t_ref;
-      q.in = res;
-      q.shape.rows = n;
-      q.shape.cols = n;
-      const bool final_here = q.stage == chain_hops;
+      p.prev = p.f;
+      p.in = res;
+      p.shape.rows = n;
+      p.shape.cols = n;
+      p.stage += 1;
+      const bool final_here = p.stage == chain_hops;
       caf_future* f = nullptr;
-      int st = caf_gpu_request(sys, hop_actor[p.stage], m.sender, &q.shape, sizeof q.shape, &q.in,
-                               1, (final_here && m.out.data) ? &m.out : nullptr, 0, &f);
-      if (st != CAF_OK) {
-        caf_future_release(q.prev);
-        if (status) status[p.idx] = st;
-        if (first_err == CAF_OK) first_err = st;
-        ++done;
-        return false;
+      const int st = cafgpu_request_tagged(sys, hop_actor[p.stage - 1], m.sender, &p.shape,
+                                           sizeof p.shape, &p.in, 1,
+                                           (final_here && m.out.data) ? &m.out : nullptr, 0, &f,
+                                           &q, k);
+      if (st == CAF_OK) {
+        p.f = f;
+        return;
       }
-      q.f = f;
-      p = q;
-      return true;
+      caf_future_release(p.prev);
+      p.prev = nullptr;
+      fail(p.idx, st);
+      free_tags.push_back(k);
+      return;
     }
     if (status) status[p.idx] = rs;
     if (latency_ns) latency_ns[p.idx] = cafgpu_future_done_ns(p.f) - p.t_ref;
     caf_future_release(p.f);
+    p.f = nullptr;
     ++done;
-    return false;
+    free_tags.push_back(k);
   };
 
   auto harvest = [&]() -> bool {
     bool any = false;
-    for (size_t k = 0; k < pend.size();) {
-      if (caf_future_poll(pend[k].f, nullptr, nullptr) == 1) {
-        any = true;
-        if (on_reply(pend[k])) {
-          ++k;
-        } else {
-          pend[k] = pend.back();
-          pend.pop_back();
-        }
-      } else {
-        ++k;
-      }
+    const uint64_t tail = __atomic_load_n(&q.tail, __ATOMIC_ACQUIRE);
+    while (q.head < tail) {
+      const uint32_t k = q.buf[q.head & q.mask];
+      q.head += 1;
+      on_reply(k);
+      any = true;
     }
     return any;
   };
 
-  if (!arrival_ns) {
-    while (done < count) {
-      while (next < count && pend.size() < window) {
-        const int64_t t = now_ns();
-        issue_first(next, t);
-        if (!pend.empty() && pend.back().idx == next)
-          pend.back().t_ref = cafgpu_future_issue_ns(pend.back().f);
-        ++next;
+  while (done < count) {
+    bool issued = false;
+    if (!arrival_ns) {
+      while (next < count && !free_tags.empty()) {
+        issue_first(next++, -1);
+        issued = true;
       }
-      if (!harvest()) _mm_pause();
-    }
-  } else {
-    while (done < count) {
+    } else {
       const int64_t now = now_ns() - t_start;
-      bool issued = false;
-      while (next < count && arrival_ns[next] <= now && pend.size() < window) {
+      while (next < count && arrival_ns[next] <= now && !free_tags.empty()) {
         issue_first(next, t_start + arrival_ns[next]);
         ++next;
         issued = true;
       }
-      if (!harvest() && !issued) _mm_pause();
     }
+    if (!harvest() && !issued) _mm_pause();
   }
   if (elapsed_s) *elapsed_s = (double)(now_ns() - t_start) * 1e-9;
   return first_err;

@@ -14,18 +14,21 @@
 //    into device-resident slots, checks each actor is alive, groups the
 //    batch (by behaviour, largest GEMMs first, or mailbox order), prefix-sums
 //    the per-message work-tile counts into one global tile sequence and
-//    publishes it.  Every workgroup claims tiles of that sequence one at a
-//    time with a compare-and-swap bounded by the published count, so no
+//    publishes it.  Every workgroup claims tiles of that sequence with a
+//    fetch_add on a claim cursor (see "claiming work tiles" below), and no
 //    workgroup ever waits for one that may not be resident.  The
 //    workgroup finishing a message's last tile either publishes its reply
 //    (a completion record in host memory, released at system scope) or
 //    forwards the reply to the next actor of a pipeline as a new message
 //    on the device (no host round trip).
 //
-//    Batched mode: the kernel exits once the ring is empty and no work is
-//    claimable.  Persistent mode: it stays resident, backing off while
-//    idle, and exits at the stop flag or after idle_ticks without work.
-//    Every device-side wait is bounded by wait_ticks of the wall clock.
+//    A launch retires as a whole once it has been idle for idle_ticks with
+//    an empty mailbox (batched mode: tens of microseconds, so one launch
+//    serves one burst; persistent mode: a long idle period) or at the stop
+//    flag.  Launches alternate between two streams, so a new launch can
+//    start while the previous one finishes its last tiles; launches share
+//    all counters and cooperate.  Every device-side wait is bounded by
+//    wait_ticks of the wall clock.
 //
 // Requests are FIFO per (sender, actor) because the host appends to the
 // ring in call order and the drain preserves each actor's relative order;
@@ -35,6 +38,12 @@
 
 #include "caf_internal.h"
 #include "tiles.h"
+
+// Rarely executed paths are kept out of line so their registers do not add
+// to the tile loop's.
+#ifndef CAF_RARE
+#define CAF_RARE __device__ __noinline__
+#endif
 
 namespace cafgpu {
 
@@ -140,7 +149,7 @@ __device__ void unlock_drain(const KArgs& a) { st_dev_rel(&a.dctl->drain_lock, 0
 
 // Forwards the finished reply of `d` to the next actor of its pipeline as a
 // new message in the same slot (thread-level, drain kernel only).
-__device__ __noinline__ void forward_reply(const KArgs& a, const Desc& d) {
+CAF_RARE void forward_reply(const KArgs& a, const Desc& d) {
   const uint32_t slot = d.slot;
   const uint32_t hop = d.hop_actor[0];
   const uint32_t actor = (hop & 0xFFFFu) - 1u;
@@ -183,9 +192,10 @@ __device__ void finish_tile(const KArgs& a, const Desc& d, uint32_t ntiles, bool
   const uint32_t slot = d.slot;
   SlotState* ss = &a.sstate[slot];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  const uint32_t prev = __hip_atomic_fetch_add(&ss->done, 1u, __ATOMIC_ACQ_REL,
+  const uint32_t prev = __hip_atomic_fetch_add(&ss->done, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
   if (prev + 1 == ntiles) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int32_t st = ld_dev(&ss->status);
     st_dev(&ss->done, 0u);
     st_dev(&ss->decision, 0u);
@@ -193,12 +203,11 @@ __device__ void finish_tile(const KArgs& a, const Desc& d, uint32_t ntiles, bool
       forward_reply(a, d);
     } else if (!(d.flags & DF_NO_COMPLETE)) {
       st_dev(&ss->status, 0);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const uint8_t* data = (d.flags & DF_INLINE_OUT) ? a.slots[slot].inline_out : nullptr;
       write_completion(a, d.req_id, st, data);
     }
   }
-  if (ring) __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELEASE,
+  if (ring) __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -223,6 +232,9 @@ __device__ void hash_step(const KArgs& a, const Desc& d) {
   st_dev_rel(&act->seq_done, d.seq + 1u);
 }
 
+// kFull = false compiles every behaviour except GEMM: without the matrix
+// tiles the kernel needs far fewer registers and runs more waves per SIMD.
+template <bool kFull>
 __device__ void run_tile(const KArgs& a, const Desc& d, uint32_t tile, uint8_t* smem,
                          uint32_t* lds_ctr) {
   switch (d.behavior) {
@@ -231,17 +243,22 @@ __device__ void run_tile(const KArgs& a, const Desc& d, uint32_t tile, uint8_t* 
       else mandel_tile<float>(d, tile, lds_ctr);
       break;
     case CAF_BHV_GEMM: {
-      float* C = reinterpret_cast<float*>(d.out);
-      if (d.flags & DF_BF16) {
-        const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
-        const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
-        if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
-        else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
+      if constexpr (kFull) {
+        float* C = reinterpret_cast<float*>(d.out);
+        if (d.flags & DF_BF16) {
+          const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
+          const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
+          if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
+          else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
+        } else {
+          const float* A = reinterpret_cast<const float*>(d.in0);
+          const float* B = reinterpret_cast<const float*>(d.in1);
+          if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, (float*)smem);
+          else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, (float*)smem);
+        }
       } else {
-        const float* A = reinterpret_cast<const float*>(d.in0);
-        const float* B = reinterpret_cast<const float*>(d.in1);
-        if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, (float*)smem);
-        else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, (float*)smem);
+        // never reached: a light launch does not drain GEMM messages
+        if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_DEVICE);
       }
       break;
     }
@@ -272,6 +289,7 @@ constexpr uint32_t kSmemBytes = 2 * 128 * 40 * 2;  // largest tile: bf16 GEMM, T
 
 // ---- one launch per message -------------------------------------------------
 
+template <bool kFull>
 __global__ void __launch_bounds__(kThreads) plain_kernel(KArgs a, Desc d, uint32_t ntiles) {
   __shared__ __align__(16) uint8_t smem[kSmemBytes];
   __shared__ uint32_t s_dec;
@@ -296,7 +314,7 @@ __global__ void __launch_bounds__(kThreads) plain_kernel(KArgs a, Desc d, uint32
     s_dec = (dec == 1 && ld_dev(&ss->status) == CAF_OK) ? 1u : 0u;
   }
   __syncthreads();
-  if (s_dec) run_tile(a, d, blockIdx.x, smem, &s_ctr);
+  if (s_dec) run_tile<kFull>(a, d, blockIdx.x, smem, &s_ctr);
   __syncthreads();
   if (threadIdx.x == 0) finish_tile(a, d, ntiles, false);
 }
@@ -324,6 +342,7 @@ struct DrainLds {
   uint16_t pos[kMaxBatch];
   uint8_t key[kMaxBatch];
   uint8_t dead[kMaxBatch];
+  uint32_t first_bad;  // light launch: first entry it cannot run
   uint32_t alive[kAliveWords];
   uint32_t hist[kKeys];
   uint32_t running[kKeys];
@@ -372,27 +391,30 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
 // Drains one batch from the mailbox (whole workgroup; the caller holds the
 // drain lock, which is released here).  Returns true if anything was drained.
 // Kept out of line so its registers do not add to the tile loop's.
-__device__ __noinline__ bool drain_once(const KArgs& a, DrainLds& L) {
+CAF_RARE bool drain_once(const KArgs& a, DrainLds& L) {
   const uint32_t t = threadIdx.x;
+  // One PCIe round trip: the ring tail, the stop flag and the actors' alive
+  // bits are read together.
+  if (t < kAliveWords) L.alive[t] = ld_sys(&a.hctl->alive[t]);
   if (t == 0) {
     const uint64_t tail = ld_sys_acq(&a.hctl->tail);
+    const uint32_t stop = ld_sys(&a.hctl->stop);
     const uint64_t d = ld_dev_acq(&a.dctl->drained);
     const uint64_t avail = tail - d;
     L.d = d;
     L.cnt = avail < a.max_batch ? avail : a.max_batch;
     L.pub = ld_dev_acq(&a.dctl->tiles_pub);
     L.done = ld_dev_acq(&a.dctl->tiles_done);
-    if (ld_sys(&a.hctl->stop)) st_dev(&a.dctl->stop_seen, 1u);
+    if (stop) st_dev(&a.dctl->stop_seen, 1u);
   }
   if (t < kKeys) L.hist[t] = 0;
+  if (t == 0) L.first_bad = ~0u;
   __syncthreads();
   uint32_t cnt = (uint32_t)L.cnt;
   if (cnt == 0) {
     if (t == 0) unlock_drain(a);
     return false;
   }
-  if (t < kAliveWords) L.alive[t] = ld_sys(&a.hctl->alive[t]);
-  __syncthreads();
   // Copy the entries into their device slots.
   for (uint32_t i = t; i < cnt; i += kThreads) {
     const uint64_t* src = reinterpret_cast<const uint64_t*>(&a.hring[(L.d + i) % a.cap]);
@@ -407,8 +429,23 @@ __device__ __noinline__ bool drain_once(const KArgs& a, DrainLds& L) {
     L.nt[i] = alive ? desc_ntiles(e) : 0u;
     L.dead[i] = alive ? 0 : 1;
     L.key[i] = (uint8_t)(a.grouping == CAF_GROUP_LPT ? group_key(e) : 0u);
+    if (!a.full && e.behavior == CAF_BHV_GEMM) atomicMin(&L.first_bad, i);
   }
   __syncthreads();
+  if (L.first_bad < cnt) {
+    // A light launch drains only the entries before the first GEMM message
+    // and, if that is the head of the mailbox, retires so that the host
+    // starts a full launch.
+    cnt = L.first_bad;
+    if (cnt == 0) {
+      if (t == 0) {
+        st_dev(&a.dctl->retiring[a.gen & 1u], a.gen);
+        st_sys_rel(&a.hctl->retiring[a.gen & 1u], a.gen);
+        unlock_drain(a);
+      }
+      return false;
+    }
+  }
   // Flow control: keep the tile map ahead of the slowest reader by tcap/2.
   for (uint32_t i = t; i < cnt; i += kThreads) L.scan[i] = L.nt[i];
   __syncthreads();
@@ -491,68 +528,114 @@ __device__ __noinline__ bool drain_once(const KArgs& a, DrainLds& L) {
   return true;
 }
 
-// Claims the next published tile (thread-level).
-__device__ bool try_claim(const KArgs& a, uint64_t& g) {
-  uint64_t pub = ld_dev_acq(&a.dctl->tiles_pub);
-  uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
-  while (cur < pub) {
-    if (cas_dev(&a.dctl->tiles_claimed, cur, cur + 1)) {
-      g = cur;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      return true;
-    }
-    pub = ld_dev_acq(&a.dctl->tiles_pub);
-  }
-  return false;
+// ---- claiming work tiles ----------------------------------------------
+//
+// A workgroup reserves tiles of the global sequence with one fetch_add on
+// the claim cursor -- never a retried compare-and-swap, whose throughput
+// collapses when hundreds of workgroups contend -- and only when the cursor
+// is below the published count.  Racing workgroups can still overshoot:
+// an index at or beyond the published count is then a reservation that the
+// next publication fills (publications start at the published count, so the
+// next published tiles are exactly the reserved ones).  Before anyone
+// leaves (retire or stop), holders of unfilled reservations publish filler
+// tiles for every reserved index, so no index is ever abandoned and no
+// message tile is ever skipped.
+
+struct Claim {
+  uint64_t next = 0, end = 0;  // tiles [next, end) are this workgroup's
+};
+
+__device__ __forceinline__ void reserve(const KArgs& a, Claim& c) {
+  const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
+  const uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
+  if (cur >= pub) return;
+  // guided self-scheduling: large chunks while plenty is published
+  uint64_t k = (pub - cur) / (2ull * a.grid);
+  k = k < 1 ? 1 : k > 8 ? 8 : k;
+  c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  c.end = c.next + k;
+}
+
+// Publishes filler tiles for every reserved but unpublished index (caller
+// holds the drain lock).
+__device__ void fill_reservations_locked(const KArgs& a) {
+  const uint64_t pub = ld_dev_acq(&a.dctl->tiles_pub);
+  const uint64_t cl = ld_dev(&a.dctl->tiles_claimed);
+  if (cl <= pub) return;
+  for (uint64_t i = pub; i < cl; ++i) a.tile2slot[i % a.tcap] = kNopTile;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  st_dev_rel(&a.dctl->tiles_pub, cl);
 }
 
 enum : uint32_t { CMD_IDLE = 0, CMD_TILE = 1, CMD_DRAIN = 2 };
+constexpr uint32_t kSentinels = 16;
 
-__global__ void __launch_bounds__(kThreads) drain_kernel(KArgs a) {
+template <bool kFull>
+__device__ __forceinline__ void drain_body(const KArgs& a) {
   __shared__ __align__(16) uint8_t smem[kSmemBytes];
   __shared__ __align__(16) DevSlot s_slot;
-  __shared__ uint32_t s_cmd, s_exit, s_ctr;
+  __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop;
   __shared__ uint64_t s_g;
   const uint32_t t = threadIdx.x;
   uint64_t last_work = now_ticks();
   uint32_t idle_rounds = 0;
+  Claim c;  // thread 0's reservation
   for (;;) {
     if (t == 0) {
-      uint64_t g;
-      if (try_claim(a, g)) {
-        s_cmd = CMD_TILE;
-        s_g = g;
-      } else if (lock_drain(a, false)) {
-        s_cmd = CMD_DRAIN;
-      } else {
-        s_cmd = CMD_IDLE;
+      uint32_t cmd = CMD_IDLE;
+      if (c.next == c.end) reserve(a, c);
+      if (c.next < c.end) {
+        const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
+        if (c.next < pub) {
+          const uint64_t n = (c.end < pub ? c.end : pub) - c.next;
+          s_g = c.next;
+          s_k = (uint32_t)n;
+          c.next += n;
+          cmd = CMD_TILE;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
       }
+      if (cmd == CMD_IDLE && lock_drain(a, false)) cmd = CMD_DRAIN;
+      s_cmd = cmd;
     }
     __syncthreads();
     const uint32_t cmd = s_cmd;
     if (cmd == CMD_TILE) {
-      const uint64_t g = s_g;
-      if (t == 0) {
-        const uint32_t slot = ld_dev(&a.tile2slot[g % a.tcap]);
-        s_slot = a.slots[slot];
-      }
-      __syncthreads();
-      // The descriptor is the same for every lane: move it to scalar
-      // registers so the tile code sees uniform parameters.
-      Desc d;
-      {
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(&s_slot.d);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(&d);
+      const uint64_t g0 = s_g;
+      const uint32_t nk = s_k;
+      for (uint32_t j = 0; j < nk; ++j) {
+        const uint64_t g = g0 + j;
+        if (t == 0) {
+          const uint32_t slot = ld_dev(&a.tile2slot[g % a.tcap]);
+          s_nop = slot == kNopTile;
+          if (!s_nop) s_slot = a.slots[slot];
+        }
+        __syncthreads();
+        if (s_nop) {  // a filler tile: nothing to do
+          if (t == 0)
+            __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+          __syncthreads();
+          continue;
+        }
+        // The descriptor is the same for every lane: move it to scalar
+        // registers so the tile code sees uniform parameters.
+        Desc d;
+        {
+          const uint32_t* src = reinterpret_cast<const uint32_t*>(&s_slot.d);
+          uint32_t* dst = reinterpret_cast<uint32_t*>(&d);
 #pragma unroll
-        for (int q = 0; q < (int)(sizeof(Desc) / 4); ++q)
-          dst[q] = __builtin_amdgcn_readfirstlane(src[q]);
+          for (int q = 0; q < (int)(sizeof(Desc) / 4); ++q)
+            dst[q] = __builtin_amdgcn_readfirstlane(src[q]);
+        }
+        const uint32_t ntiles = __builtin_amdgcn_readfirstlane(s_slot.ntiles);
+        const uint32_t tile = (uint32_t)(g - s_slot.tile_base);
+        if (ld_dev(&a.sstate[d.slot].status) == CAF_OK) run_tile<kFull>(a, d, tile, smem, &s_ctr);
+        __syncthreads();
+        if (t == 0) finish_tile(a, d, ntiles, true);
+        __syncthreads();
       }
-      const uint32_t ntiles = __builtin_amdgcn_readfirstlane(s_slot.ntiles);
-      const uint32_t tile = (uint32_t)(g - s_slot.tile_base);
-      if (ld_dev(&a.sstate[d.slot].status) == CAF_OK) run_tile(a, d, tile, smem, &s_ctr);
-      __syncthreads();
-      if (t == 0) finish_tile(a, d, ntiles, true);
-      __syncthreads();
       last_work = now_ticks();
       idle_rounds = 0;
       continue;
@@ -568,20 +651,39 @@ __global__ void __launch_bounds__(kThreads) drain_kernel(KArgs a) {
     }
     if (t == 0) {
       uint32_t ex = 0;
-      if (ld_dev(&a.dctl->stop_seen)) {
+      const uint32_t par = a.gen & 1u;
+      const bool holding = c.next < c.end;  // reserved, not yet published
+      const bool leaving =
+          ld_dev(&a.dctl->stop_seen) || ld_dev(&a.dctl->retiring[par]) == a.gen;
+      if (holding) {
+        // Nobody may leave an index unexecuted: before this launch goes (or
+        // once this workgroup has idled as long as a launch may linger),
+        // fill the outstanding reservations with filler tiles.
+        if ((leaving || now_ticks() - last_work > a.idle_ticks) && lock_drain(a, true)) {
+          fill_reservations_locked(a);
+          unlock_drain(a);
+        }
+      } else if (leaving) {
         ex = 1;
-      } else if (a.exit_on_empty) {
-        if (ld_dev(&a.dctl->tiles_claimed) >= ld_dev_acq(&a.dctl->tiles_pub) &&
-            ld_dev(&a.dctl->drain_lock) == 0 &&
-            ld_sys_acq(&a.hctl->tail) == ld_dev_acq(&a.dctl->drained) &&
-            ld_dev(&a.dctl->tiles_claimed) >= ld_dev_acq(&a.dctl->tiles_pub))
-          ex = 1;
-      } else if (now_ticks() - last_work > a.idle_ticks) {
+      } else if (blockIdx.x < kSentinels && now_ticks() - last_work > a.idle_ticks &&
+                 ld_dev(&a.dctl->tiles_claimed) >= ld_dev(&a.dctl->tiles_pub) &&
+                 ld_dev(&a.dctl->drain_lock) == 0 &&
+                 ld_sys_acq(&a.hctl->tail) == ld_dev_acq(&a.dctl->drained)) {
+        // Idle long enough with an empty mailbox: retire this launch.  Every
+        // workgroup of it leaves once it holds no work (claimed tiles are
+        // finished first), and the host starts a new launch when messages
+        // arrive.  Batched mode lingers a few tens of microseconds,
+        // persistent mode much longer.
+        st_dev(&a.dctl->retiring[par], a.gen);
+        st_sys_rel(&a.hctl->retiring[par], a.gen);
         ex = 1;
       }
       s_exit = ex;
       if (!ex) {
-        idle_rounds = idle_rounds < 8 ? idle_rounds + 1 : 8;
+        // A few sentinel workgroups poll with a short back-off (reply
+        // latency); the rest back off further while idle.
+        const uint32_t cap = blockIdx.x < kSentinels ? 1u : 8u;
+        idle_rounds = idle_rounds < cap ? idle_rounds + 1 : cap;
         backoff_sleep(idle_rounds);
       }
     }
@@ -589,29 +691,46 @@ __global__ void __launch_bounds__(kThreads) drain_kernel(KArgs a) {
     if (s_exit) break;
   }
   if (t == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(&a.dctl->wg_exited, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t par = a.gen & 1u;
+    const uint32_t prev = __hip_atomic_fetch_add(&a.dctl->wg_exited[par], 1u,
+                                                 __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (prev + 1 == a.grid) {
-      st_dev(&a.dctl->wg_exited, 0u);
-      st_sys_rel(&a.hctl->exited_gen, a.gen);
+      st_dev(&a.dctl->wg_exited[par], 0u);
+      st_sys_rel(&a.hctl->exited[par], a.gen);
     }
   }
+}
+
+__global__ void __launch_bounds__(kThreads) drain_kernel_full(KArgs a) { drain_body<true>(a); }
+
+// The light variant asks for five waves per SIMD (at most 96 registers).
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
+drain_kernel_light(KArgs a) {
+  drain_body<false>(a);
 }
 
 // ---- host-side launch wrappers ------------------------------------------
 
 hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s) {
-  hipLaunchKernelGGL(plain_kernel, dim3(ntiles), dim3(kThreads), 0, s, a, d, ntiles);
+  if (d.behavior == CAF_BHV_GEMM)
+    hipLaunchKernelGGL(plain_kernel<true>, dim3(ntiles), dim3(kThreads), 0, s, a, d, ntiles);
+  else
+    hipLaunchKernelGGL(plain_kernel<false>, dim3(ntiles), dim3(kThreads), 0, s, a, d, ntiles);
   return hipGetLastError();
 }
 
 hipError_t launch_drain(const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(drain_kernel, dim3(a.grid), dim3(kThreads), 0, s, a);
+  if (a.full) hipLaunchKernelGGL(drain_kernel_full, dim3(a.grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(drain_kernel_light, dim3(a.grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t drain_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel, kThreads, 0);
+hipError_t drain_occupancy(bool full, int* blocks_per_cu) {
+  if (full)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel_full,
+                                                        kThreads, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel_light,
+                                                      kThreads, 0);
 }
 
 }  // namespace cafgpu

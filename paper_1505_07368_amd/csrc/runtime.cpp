@@ -10,6 +10,11 @@
 // interfaces checked per message (Sec. 4.5), sync_send / then with unique
 // request ids, errors and timeouts (Sec. 5), call-by-value messages
 // (Sec. 4.4), the actor life cycle and max_msgs per run (Sec. 6).
+//
+// Concurrency: one mutex (`mu`) guards the actor table, the slot pool, the
+// arena and the ring writer; a request takes it once in the common case.
+// The poller resolves completions in batches, taking the mutex once per
+// batch.
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
@@ -28,7 +33,7 @@
 namespace cafgpu {
 hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s);
 hipError_t launch_drain(const KArgs& a, hipStream_t s);
-hipError_t drain_occupancy(int* blocks_per_cu);
+hipError_t drain_occupancy(bool full, int* blocks_per_cu);
 }  // namespace cafgpu
 
 using namespace cafgpu;
@@ -37,6 +42,8 @@ namespace {
 
 constexpr uint64_t kGranule = 256;
 constexpr uint32_t kTileMapCap = 1u << 22;
+constexpr uint32_t kMaxTemps = 6;
+constexpr uint32_t kPollBatch = 256;
 
 inline int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -44,7 +51,8 @@ inline int64_t now_ns() {
       .count();
 }
 
-// Best-fit sub-allocator over the caller's arena, with coalescing.
+// Best-fit sub-allocator over the caller's arena, with coalescing.  Not
+// synchronised: every call is made with the system mutex held.
 class Arena {
  public:
   void init(uint64_t base, uint64_t bytes) {
@@ -54,13 +62,15 @@ class Arena {
     by_size_.clear();
     insert(0, size_);
   }
+  static uint64_t granules(uint64_t bytes) {
+    const uint64_t need = (bytes + kGranule - 1) / kGranule * kGranule;
+    return need ? need : kGranule;
+  }
   bool alloc(uint64_t bytes, uint64_t* addr) {
-    uint64_t need = (bytes + kGranule - 1) / kGranule * kGranule;
-    if (need == 0) need = kGranule;
-    std::lock_guard<std::mutex> g(mu_);
+    const uint64_t need = granules(bytes);
     auto it = by_size_.lower_bound(need);
     if (it == by_size_.end()) return false;
-    uint64_t sz = it->first, off = it->second;
+    const uint64_t sz = it->first, off = it->second;
     erase(off, sz);
     if (sz > need) insert(off + need, sz - need);
     in_use_ += need;
@@ -69,14 +79,11 @@ class Arena {
     return true;
   }
   void free(uint64_t addr, uint64_t bytes) {
-    uint64_t need = (bytes + kGranule - 1) / kGranule * kGranule;
-    if (need == 0) need = kGranule;
-    std::lock_guard<std::mutex> g(mu_);
-    uint64_t off = addr - base_, sz = need;
-    in_use_ -= need;
+    uint64_t off = addr - base_, sz = granules(bytes);
+    in_use_ -= sz;
     auto nx = by_off_.lower_bound(off);
     if (nx != by_off_.end() && nx->first == off + sz) {
-      uint64_t nsz = nx->second;
+      const uint64_t nsz = nx->second;
       erase(nx->first, nsz);
       sz += nsz;
     }
@@ -84,7 +91,7 @@ class Arena {
     if (pv != by_off_.begin()) {
       --pv;
       if (pv->first + pv->second == off) {
-        uint64_t poff = pv->first, psz = pv->second;
+        const uint64_t poff = pv->first, psz = pv->second;
         erase(poff, psz);
         off = poff;
         sz += psz;
@@ -92,14 +99,8 @@ class Arena {
     }
     insert(off, sz);
   }
-  uint64_t in_use() {
-    std::lock_guard<std::mutex> g(mu_);
-    return in_use_;
-  }
-  uint64_t peak() {
-    std::lock_guard<std::mutex> g(mu_);
-    return peak_;
-  }
+  uint64_t in_use() const { return in_use_; }
+  uint64_t peak() const { return peak_; }
 
  private:
   void insert(uint64_t off, uint64_t sz) {
@@ -115,7 +116,6 @@ class Arena {
         break;
       }
   }
-  std::mutex mu_;
   uint64_t base_ = 0, size_ = 0, in_use_ = 0, peak_ = 0;
   std::map<uint64_t, uint64_t> by_off_;
   std::multimap<uint64_t, uint64_t> by_size_;
@@ -156,19 +156,24 @@ struct caf_future {
   Block out;                  // arena reply buffer owned by this future
   std::atomic<int> refs{2};   // the caller's handle + the request in flight
   int64_t t_issue = 0, t_done = 0;
+  DriveQ* q = nullptr;        // driver notification (optional)
+  uint32_t tag = 0;
+  bool pooled = false;
 };
 
 struct SlotInfo {
   uint64_t req_id = 0;
   caf_future* fut = nullptr;
-  std::vector<Block> temps;  // staged inputs, intermediate replies, unwanted replies
+  Block temps[kMaxTemps];  // staged inputs, intermediate and unwanted replies
+  uint32_t ntemps = 0;
 };
 
 struct caf_gpu_system {
   caf_gpu_config cfg{};
   int device = 0;
-  hipStream_t stream = nullptr, dstream = nullptr;
-  bool own_stream = false, own_dstream = false;
+  hipStream_t stream = nullptr;
+  hipStream_t dstream[2] = {nullptr, nullptr};  // drain launches alternate between these
+  bool own_stream = false, own_dstream[2] = {false, false};
   // host memory shared with the device
   HostCtl* hctl = nullptr;
   Desc* hring = nullptr;
@@ -180,20 +185,24 @@ struct caf_gpu_system {
   uint32_t* tile2slot = nullptr;
   DevActor* dactors = nullptr;
   KArgs kargs{};
-  Arena arena;
   uint32_t cap = 0;
-  // actor table, slots, mailbox
+  // guarded by mu
   std::mutex mu;
   std::condition_variable cv_space;
+  Arena arena;
   std::vector<ActorRec> actors;
   std::vector<SlotInfo> slots;
   std::vector<uint32_t> free_slots;
+  std::vector<caf_future*> fut_pool;
+  std::vector<caf_future*> all_futs;  // every future object, for shutdown
   uint64_t tail = 0;
   uint64_t req_seq = 1;
+  bool shut = false;
   std::atomic<uint64_t> outstanding{0};
+  std::atomic<uint32_t> waiters{0};
   // drain kernel
   std::mutex launch_mu;
-  uint32_t launched_gen = 0;
+  std::atomic<uint32_t> launched_gen{0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
   // poller
@@ -204,24 +213,64 @@ struct caf_gpu_system {
       st_drain_launches{0}, st_dup{0}, st_swallowed{0}, st_rejected{0};
   uint32_t mandel_tile_px = 1024;
   uint32_t gemm_tile = 0;
-  bool shut = false;
+  uint32_t grid_full = 0, grid_light = 0;  // drain-kernel workgroups per variant
+  std::atomic<bool> need_full{false};       // a GEMM actor exists
 };
 
 namespace {
 
-void put_ref(caf_future* f) {
-  if (f->refs.fetch_sub(1) == 1) {
-    if (f->out.bytes) f->sys->arena.free(f->out.addr, f->out.bytes);
-    delete f;
+caf_future* new_future(caf_gpu_system* s) {  // mu held
+  caf_future* f;
+  if (!s->fut_pool.empty()) {
+    f = s->fut_pool.back();
+    s->fut_pool.pop_back();
+  } else {
+    f = new caf_future();
+    s->all_futs.push_back(f);
+  }
+  f->pooled = false;
+  f->sys = s;
+  f->req_id = 0;
+  f->state.store(0, std::memory_order_relaxed);
+  f->status = 0;
+  f->result = caf_buf{};
+  f->out = Block{};
+  f->refs.store(2, std::memory_order_relaxed);
+  f->t_issue = f->t_done = 0;
+  f->q = nullptr;
+  f->tag = 0;
+  return f;
+}
+
+void put_ref(caf_future* f) {  // mu not held
+  if (f->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+    caf_gpu_system* s = f->sys;
+    if (!s) {  // orphaned by caf_gpu_shutdown
+      delete f;
+      return;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
+    f->out = Block{};
+    f->pooled = true;
+    s->fut_pool.push_back(f);
+    if (s->waiters.load(std::memory_order_relaxed)) s->cv_space.notify_all();
   }
 }
 
+// True while the latest drain launch serves the mailbox (neither retiring
+// nor exited).
 bool drain_running(caf_gpu_system* s) {
-  return __atomic_load_n(&s->hctl->exited_gen, __ATOMIC_ACQUIRE) != s->launched_gen;
+  const uint32_t g = s->launched_gen.load(std::memory_order_acquire);
+  if (g == 0) return false;
+  const uint32_t p = g & 1u;
+  return __atomic_load_n(&s->hctl->retiring[p], __ATOMIC_ACQUIRE) != g &&
+         __atomic_load_n(&s->hctl->exited[p], __ATOMIC_ACQUIRE) != g;
 }
 
 // Launches the drain kernel if it is not running (ring modes).
 void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
+  if (drain_running(s)) return;  // fast path, no lock
   std::lock_guard<std::mutex> g(s->launch_mu);
   if (drain_running(s)) return;
   if (only_if_pending &&
@@ -229,7 +278,9 @@ void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
           __atomic_load_n(&s->hctl->tail, __ATOMIC_ACQUIRE))
     return;
   KArgs a = s->kargs;
-  a.gen = ++s->launched_gen;
+  a.gen = s->launched_gen.load() + 1;
+  a.full = s->need_full.load() ? 1u : 0u;
+  a.grid = a.full ? s->grid_full : s->grid_light;
   // Launch windows are timed with events until the pool is full.
   if (s->ev_used == s->ev_pool.size() && s->ev_pool.size() < 16384) {
     hipEvent_t e0, e1;
@@ -237,64 +288,97 @@ void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
     hipEventCreate(&e1);
     s->ev_pool.emplace_back(e0, e1);
   }
+  // The previous launch may still be finishing its last tiles on the other
+  // stream; launches cooperate through the shared counters.
+  hipStream_t st = s->dstream[a.gen & 1u];
   const bool timed = s->ev_used < s->ev_pool.size();
-  if (timed) hipEventRecord(s->ev_pool[s->ev_used].first, s->dstream);
-  hipError_t e = launch_drain(a, s->dstream);
-  if (e != hipSuccess) std::fprintf(stderr, "cafgpu: drain launch failed: %s\n", hipGetErrorString(e));
-  if (timed) hipEventRecord(s->ev_pool[s->ev_used++].second, s->dstream);
+  if (timed) hipEventRecord(s->ev_pool[s->ev_used].first, st);
+  const hipError_t e = launch_drain(a, st);
+  if (e != hipSuccess) {
+    std::fprintf(stderr, "cafgpu: drain launch failed: %s\n", hipGetErrorString(e));
+    return;
+  }
+  if (timed) hipEventRecord(s->ev_pool[s->ev_used++].second, st);
+  s->launched_gen.store(a.gen, std::memory_order_release);
   s->st_drain_launches++;
 }
 
-void resolve_slot(caf_gpu_system* s, const Comp& c) {
-  const uint32_t slot = (uint32_t)(c.req_id & (kMaxSlots - 1));
-  caf_future* f = nullptr;
-  std::vector<Block> temps;
+// Resolves a batch of completion records (poller thread).
+void resolve_batch(caf_gpu_system* s, const Comp* recs, uint32_t n) {
+  caf_future* futs[kPollBatch];
+  const Comp* frec[kPollBatch];
+  uint32_t nf = 0, valid = 0;
   {
     std::lock_guard<std::mutex> g(s->mu);
-    if (slot >= s->cap || s->slots[slot].req_id != c.req_id) {
-      s->st_dup++;
-      return;
+    for (uint32_t i = 0; i < n; ++i) {
+      const Comp& c = recs[i];
+      const uint32_t slot = (uint32_t)(c.req_id & (kMaxSlots - 1));
+      if (slot >= s->cap || s->slots[slot].req_id != c.req_id) {
+        s->st_dup++;
+        continue;
+      }
+      SlotInfo& si = s->slots[slot];
+      for (uint32_t k = 0; k < si.ntemps; ++k) s->arena.free(si.temps[k].addr, si.temps[k].bytes);
+      si.ntemps = 0;
+      if (si.fut) {
+        futs[nf] = si.fut;
+        frec[nf] = &c;
+        ++nf;
+      }
+      si.fut = nullptr;
+      si.req_id = 0;
+      s->free_slots.push_back(slot);
+      ++valid;
     }
-    SlotInfo& si = s->slots[slot];
-    f = si.fut;
-    temps.swap(si.temps);
-    si.fut = nullptr;
-    si.req_id = 0;
-    s->free_slots.push_back(slot);
   }
-  for (auto& b : temps) s->arena.free(b.addr, b.bytes);
-  s->st_completions++;
-  if (f) {
-    f->status = c.status;
+  s->st_completions += valid;
+  const int64_t t = now_ns();
+  for (uint32_t i = 0; i < nf; ++i) {
+    caf_future* f = futs[i];
+    f->status = frec[i]->status;
     if (f->result.on_device == 0 && f->result.data == f->inline_data)
-      std::memcpy(f->inline_data, c.data, kInlineBytes);
-    f->t_done = now_ns();
+      std::memcpy(f->inline_data, frec[i]->data, kInlineBytes);
+    f->t_done = t;
     int expect = 0;
-    if (!f->state.compare_exchange_strong(expect, 1)) s->st_swallowed++;
+    if (f->state.compare_exchange_strong(expect, 1, std::memory_order_acq_rel)) {
+      if (f->q) {
+        DriveQ* q = f->q;
+        const uint64_t tl = __atomic_load_n(&q->tail, __ATOMIC_RELAXED);
+        q->buf[tl & q->mask] = f->tag;
+        __atomic_store_n(&q->tail, tl + 1, __ATOMIC_RELEASE);
+      }
+    } else {
+      s->st_swallowed++;
+    }
     put_ref(f);
   }
-  s->outstanding.fetch_sub(1);
-  s->cv_space.notify_all();
+  s->outstanding.fetch_sub(valid, std::memory_order_acq_rel);
+  if (s->waiters.load(std::memory_order_relaxed)) s->cv_space.notify_all();
 }
 
 void poller_main(caf_gpu_system* s) {
   hipSetDevice(s->device);
   uint32_t idle = 0;
   const uint32_t ccap = s->cap;
+  Comp batch[kPollBatch];
   while (!s->stop_poller.load(std::memory_order_relaxed)) {
-    Comp* c = &s->comp[s->comp_head % ccap];
-    const uint32_t lap = (uint32_t)(s->comp_head / ccap) + 1;
-    if (__atomic_load_n(&c->lap, __ATOMIC_ACQUIRE) == lap) {
-      Comp copy;
-      std::memcpy(&copy, c, sizeof copy);
+    uint32_t n = 0;
+    while (n < kPollBatch) {
+      const Comp* c = &s->comp[s->comp_head % ccap];
+      const uint32_t lap = (uint32_t)(s->comp_head / ccap) + 1;
+      if (__atomic_load_n(&c->lap, __ATOMIC_ACQUIRE) != lap) break;
+      std::memcpy(&batch[n], c, sizeof(Comp));
       s->comp_head++;
-      resolve_slot(s, copy);
+      ++n;
+    }
+    if (n) {
+      resolve_batch(s, batch, n);
       idle = 0;
       continue;
     }
     if (s->cfg.mode != CAF_MODE_PLAIN && (idle & 63) == 0) ensure_drain(s, true);
     ++idle;
-    if (idle < 20000 || s->outstanding.load() != 0) {
+    if (idle < 20000 || s->outstanding.load(std::memory_order_relaxed) != 0) {
       _mm_pause();
     } else {
       std::this_thread::sleep_for(std::chrono::microseconds(50));
@@ -379,23 +463,87 @@ uint32_t gemm_tile_for(const caf_gpu_system* s, uint32_t n) {
   return n <= 128 ? 64u : 128u;
 }
 
+// Builds the descriptor of the first stage (all fields except slot, seq and
+// request id).
+void fill_desc(const caf_gpu_system* s, const ActorRec& a, uint32_t aidx, const void* args,
+               const caf_buf* in, bool inline_in, bool inline_out, bool is_request, Desc* d) {
+  std::memset(d, 0, sizeof *d);
+  d->actor = aidx;
+  d->behavior = (uint16_t)a.behavior;
+  switch (a.behavior) {
+    case CAF_BHV_MANDELBROT: {
+      const caf_mandel_args* m = (const caf_mandel_args*)args;
+      if (m->fp == CAF_F64) {
+        d->flags |= DF_FP64;
+        d->p.m64.re_min = m->re_min;
+        d->p.m64.im_min = m->im_min;
+        d->p.m64.step_re = m->step_re;
+        d->p.m64.step_im = m->step_im;
+      } else {
+        // float messages: the viewport doubles are rounded to float once
+        d->p.m32.re_min = (float)m->re_min;
+        d->p.m32.im_min = (float)m->im_min;
+        d->p.m32.step_re = (float)m->step_re;
+        d->p.m32.step_im = (float)m->step_im;
+      }
+      d->p.m64.width = m->width;
+      d->p.m64.row0 = m->row0;
+      d->p.m64.rows = m->rows;
+      d->p.m64.max_iter = m->max_iter;
+      d->tcfg = s->mandel_tile_px;
+      break;
+    }
+    case CAF_BHV_GEMM: {
+      const caf_gemm_args* g = (const caf_gemm_args*)args;
+      if (g->in_dtype == CAF_BF16) d->flags |= DF_BF16;
+      d->p.g.n = g->n;
+      d->tcfg = gemm_tile_for(s, g->n);
+      break;
+    }
+    case CAF_BHV_TANH:
+    case CAF_BHV_ROWSUM: {
+      const caf_shape_args* x = (const caf_shape_args*)args;
+      d->p.s.rows = x->rows;
+      d->p.s.cols = x->cols;
+      break;
+    }
+    case CAF_BHV_HASHCHAIN:
+      d->p.h.x = ((const caf_hash_args*)args)->x;
+      break;
+    case CAF_BHV_NOOP:
+      d->numel = (uint32_t)in[0].numel;
+      if (inline_in) {
+        d->flags |= DF_INLINE_IN;
+        std::memcpy(d->p.raw, in[0].data, in[0].numel * 4);
+      }
+      break;
+    default:
+      break;
+  }
+  if (inline_out) d->flags |= DF_INLINE_OUT;
+  if (!is_request) d->flags |= DF_SEND;
+}
+
 int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
            uint64_t args_bytes, const caf_buf* in, uint32_t n_in, const caf_buf* out_buf,
-           caf_actor forward_to, caf_future** fut, bool is_request) {
-  if (!s || s->shut) return CAF_E_INVALID;
-  if (n_in > 2) return CAF_E_INVALID;
-  ActorRec a, hop[kMaxHops];
-  uint32_t nhops = 0;
+           caf_actor forward_to, caf_future** fut, bool is_request, DriveQ* q, uint32_t tag) {
+  (void)sender;  // FIFO per (sender, actor) follows from the single ring order
+  if (!s) return CAF_E_INVALID;
+  if (n_in > 2 || (n_in && !in)) return CAF_E_INVALID;
+  const bool user_out = out_buf && out_buf->data;
+  std::unique_lock<std::mutex> g(s->mu);
+  if (s->shut) return CAF_E_INVALID;
+  // ---- signature and forwarding chain (Sec. 4.5 / 4.6) ------------------
+  if (dst == 0 || dst > s->actors.size()) return CAF_E_NO_ACTOR;
+  const uint32_t aidx = (uint32_t)(dst - 1);
+  const ActorRec a = s->actors[aidx];
+  if (!a.alive) return CAF_E_NO_ACTOR;
   Shape sh, hsh[kMaxHops];
-  uint32_t aidx = 0, hidx[kMaxHops] = {0, 0};
+  int st = check_signature(a, args, args_bytes, in, n_in, &sh);
+  if (st != CAF_OK) return st;
+  uint32_t nhops = 0, hidx[kMaxHops] = {0, 0};
+  int32_t hbeh[kMaxHops] = {0, 0};
   {
-    std::lock_guard<std::mutex> g(s->mu);
-    if (dst == 0 || dst > s->actors.size()) return CAF_E_NO_ACTOR;
-    aidx = (uint32_t)(dst - 1);
-    a = s->actors[aidx];
-    if (!a.alive) return CAF_E_NO_ACTOR;
-    int st = check_signature(a, args, args_bytes, in, n_in, &sh);
-    if (st != CAF_OK) return st;
     caf_actor next = forward_to ? forward_to : a.spawn.forward_to;
     Shape prev = sh;
     while (next) {
@@ -407,7 +555,7 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
       st = check_stage_input(h, prev.rows, prev.cols, &hsh[nhops]);
       if (st != CAF_OK) return st;
       hidx[nhops] = (uint32_t)(next - 1);
-      hop[nhops] = h;
+      hbeh[nhops] = h.behavior;
       prev = hsh[nhops];
       ++nhops;
       next = h.spawn.forward_to;
@@ -415,162 +563,101 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   }
   const Shape& final_shape = nhops ? hsh[nhops - 1] : sh;
   const uint64_t final_bytes = final_shape.numel * dtype_bytes(final_shape.dtype);
-  bool inline_in = false, inline_out = false;
-  if (a.behavior == CAF_BHV_NOOP) {
-    inline_in = !in[0].on_device && in[0].numel * 4 <= kInlineBytes;
-  }
-  if (nhops == 0 && (a.behavior == CAF_BHV_NOOP || a.behavior == CAF_BHV_HASHCHAIN) &&
-      final_bytes <= kInlineBytes && (!out_buf || !out_buf->data))
-    inline_out = true;
-  if (out_buf && out_buf->data) {
-    if (!out_buf->on_device || out_buf->dtype != final_shape.dtype ||
-        out_buf->numel != final_shape.numel)
-      return CAF_E_INVALID;
-  }
-
-  // Descriptor (everything except slot, seq and request id).
+  const bool inline_in =
+      a.behavior == CAF_BHV_NOOP && !in[0].on_device && in[0].numel * 4 <= kInlineBytes;
+  const bool inline_out = nhops == 0 &&
+                          (a.behavior == CAF_BHV_NOOP || a.behavior == CAF_BHV_HASHCHAIN) &&
+                          final_bytes <= kInlineBytes && !user_out;
+  if (user_out && (!out_buf->on_device || out_buf->dtype != final_shape.dtype ||
+                   out_buf->numel != final_shape.numel))
+    return CAF_E_INVALID;
   Desc d;
-  std::memset(&d, 0, sizeof d);
-  d.actor = aidx;
-  d.behavior = (uint16_t)a.behavior;
-  switch (a.behavior) {
-    case CAF_BHV_MANDELBROT: {
-      const caf_mandel_args* m = (const caf_mandel_args*)args;
-      if (m->fp == CAF_F64) {
-        d.flags |= DF_FP64;
-        d.p.m64.re_min = m->re_min;
-        d.p.m64.im_min = m->im_min;
-        d.p.m64.step_re = m->step_re;
-        d.p.m64.step_im = m->step_im;
-      } else {
-        // float messages: the viewport doubles are rounded to float once
-        d.p.m32.re_min = (float)m->re_min;
-        d.p.m32.im_min = (float)m->im_min;
-        d.p.m32.step_re = (float)m->step_re;
-        d.p.m32.step_im = (float)m->step_im;
-      }
-      d.p.m64.width = m->width;
-      d.p.m64.row0 = m->row0;
-      d.p.m64.rows = m->rows;
-      d.p.m64.max_iter = m->max_iter;
-      d.tcfg = s->mandel_tile_px;
-      break;
-    }
-    case CAF_BHV_GEMM: {
-      const caf_gemm_args* g = (const caf_gemm_args*)args;
-      if (g->in_dtype == CAF_BF16) d.flags |= DF_BF16;
-      d.p.g.n = g->n;
-      d.tcfg = gemm_tile_for(s, g->n);
-      break;
-    }
-    case CAF_BHV_TANH:
-    case CAF_BHV_ROWSUM: {
-      const caf_shape_args* x = (const caf_shape_args*)args;
-      d.p.s.rows = x->rows;
-      d.p.s.cols = x->cols;
-      break;
-    }
-    case CAF_BHV_HASHCHAIN:
-      d.p.h.x = ((const caf_hash_args*)args)->x;
-      break;
-    case CAF_BHV_NOOP:
-      d.numel = (uint32_t)in[0].numel;
-      if (inline_in) {
-        d.flags |= DF_INLINE_IN;
-        std::memcpy(d.p.raw, in[0].data, in[0].numel * 4);
-      }
-      break;
-    default:
-      break;
-  }
-  if (inline_out) d.flags |= DF_INLINE_OUT;
-  if (!is_request) d.flags |= DF_SEND;
+  fill_desc(s, a, aidx, args, in, inline_in, inline_out, is_request, &d);
   if (desc_ntiles(d) > kTileMapCap / 4) return CAF_E_INVALID;
   for (uint32_t h = 0; h < nhops; ++h)
-    d.hop_actor[h] = ((uint32_t)hop[h].behavior << 16) | (hidx[h] + 1);
+    d.hop_actor[h] = ((uint32_t)hbeh[h] << 16) | (hidx[h] + 1);
 
-  // Admission: a slot plus every arena buffer the message needs.
-  std::vector<Block> blocks;  // staged inputs, stage outputs
-  Block out_blk;              // final reply when library-allocated (owned by the future)
+  // ---- admission: a slot plus every arena buffer the message needs ------
+  Block staged[2];
+  Block sout[1 + kMaxHops];
   uint32_t slot = 0;
+  for (;;) {
+    bool ok = !s->free_slots.empty();
+    auto take = [&](uint64_t bytes, Block* b) {
+      if (!ok) return;
+      uint64_t addr;
+      if (!s->arena.alloc(bytes, &addr)) {
+        ok = false;
+        return;
+      }
+      *b = Block{addr, bytes};
+    };
+    for (uint32_t i = 0; i < n_in; ++i)
+      if (!in[i].on_device && !(inline_in && i == 0))
+        take(in[i].numel * dtype_bytes(in[i].dtype), &staged[i]);
+    for (uint32_t k = 0; k <= nhops; ++k) {
+      const Shape& shk = k == 0 ? sh : hsh[k - 1];
+      if (k == nhops && (inline_out || user_out)) continue;
+      const uint64_t bytes = shk.numel * dtype_bytes(shk.dtype);
+      take(bytes ? bytes : 4, &sout[k]);
+    }
+    if (ok) {
+      slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      break;
+    }
+    for (auto& b : staged)
+      if (b.bytes) s->arena.free(b.addr, b.bytes), b = Block{};
+    for (auto& b : sout)
+      if (b.bytes) s->arena.free(b.addr, b.bytes), b = Block{};
+    if (!s->cfg.blocking) {
+      s->st_rejected++;
+      return CAF_E_OVERLOAD;
+    }
+    s->waiters.fetch_add(1);
+    s->cv_space.wait_for(g, std::chrono::milliseconds(1));
+    s->waiters.fetch_sub(1);
+    if (s->shut) return CAF_E_QUIT;
+  }
   uint64_t stage_out[1 + kMaxHops] = {0, 0, 0};
-  {
-    std::unique_lock<std::mutex> g(s->mu);
-    for (;;) {
-      bool ok = !s->free_slots.empty();
-      auto take = [&](uint64_t bytes, Block* b) {
-        if (!ok) return;
-        uint64_t addr;
-        if (!s->arena.alloc(bytes, &addr)) {
-          ok = false;
-          return;
-        }
-        b->addr = addr;
-        b->bytes = bytes;
-      };
-      // inputs from host memory are staged into the arena
-      Block staged[2];
-      for (uint32_t i = 0; i < n_in; ++i)
-        if (!in[i].on_device && !(inline_in && i == 0))
-          take(in[i].numel * dtype_bytes(in[i].dtype), &staged[i]);
-      // stage outputs: stage 0 .. nhops; the last one is the reply
-      Block sout[1 + kMaxHops];
-      for (uint32_t k = 0; k <= nhops; ++k) {
-        const Shape& shk = k == 0 ? sh : hsh[k - 1];
-        const uint64_t bytes = shk.numel * dtype_bytes(shk.dtype);
-        const bool last = k == nhops;
-        if (last && (inline_out || (out_buf && out_buf->data))) continue;
-        take(bytes ? bytes : 4, &sout[k]);
-      }
-      if (ok) {
-        slot = s->free_slots.back();
-        s->free_slots.pop_back();
-        for (uint32_t i = 0; i < 2; ++i)
-          if (staged[i].bytes) blocks.push_back(staged[i]);
-        for (uint32_t k = 0; k <= nhops; ++k) {
-          if (!sout[k].bytes) continue;
-          stage_out[k] = sout[k].addr;
-          if (k == nhops && is_request) out_blk = sout[k];
-          else blocks.push_back(sout[k]);
-        }
-        break;
-      }
-      for (uint32_t i = 0; i < 2; ++i)
-        if (staged[i].bytes) s->arena.free(staged[i].addr, staged[i].bytes);
-      for (uint32_t k = 0; k <= nhops; ++k)
-        if (sout[k].bytes) s->arena.free(sout[k].addr, sout[k].bytes);
-      if (!s->cfg.blocking) {
-        s->st_rejected++;
-        return CAF_E_OVERLOAD;
-      }
-      s->cv_space.wait_for(g, std::chrono::milliseconds(1));
-      if (s->shut) return CAF_E_QUIT;
+  for (uint32_t k = 0; k <= nhops; ++k) stage_out[k] = sout[k].addr;
+  if (user_out) stage_out[nhops] = (uint64_t)(uintptr_t)out_buf->data;
+
+  // ---- inputs: device pointers as given; host inputs are copied before
+  // the message becomes visible to the device (call-by-value, Sec. 4.4)
+  uint64_t inptr[2] = {0, 0};
+  bool staging = false;
+  for (uint32_t i = 0; i < n_in; ++i) {
+    if (inline_in && i == 0) continue;
+    if (in[i].on_device) inptr[i] = (uint64_t)(uintptr_t)in[i].data;
+    else {
+      inptr[i] = staged[i].addr;
+      staging = true;
     }
   }
-  if (out_buf && out_buf->data) stage_out[nhops] = (uint64_t)(uintptr_t)out_buf->data;
-
-  // Inputs: device pointers as given, host inputs copied (synchronously,
-  // before the message becomes visible to the device).
-  uint64_t inptr[2] = {0, 0};
-  {
-    size_t bi = 0;
-    for (uint32_t i = 0; i < n_in; ++i) {
-      if (inline_in && i == 0) continue;
-      if (in[i].on_device) {
-        inptr[i] = (uint64_t)(uintptr_t)in[i].data;
-      } else {
-        const Block& b = blocks[bi++];
-        inptr[i] = b.addr;
-        hipError_t e = hipMemcpy((void*)(uintptr_t)b.addr, in[i].data,
-                                 in[i].numel * dtype_bytes(in[i].dtype), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-          std::lock_guard<std::mutex> g(s->mu);
-          for (auto& bb : blocks) s->arena.free(bb.addr, bb.bytes);
-          if (out_blk.bytes) s->arena.free(out_blk.addr, out_blk.bytes);
-          s->free_slots.push_back(slot);
-          return CAF_E_DEVICE;
-        }
-      }
+  auto release_all = [&]() {
+    for (auto& b : staged)
+      if (b.bytes) s->arena.free(b.addr, b.bytes);
+    for (auto& b : sout)
+      if (b.bytes) s->arena.free(b.addr, b.bytes);
+    s->free_slots.push_back(slot);
+  };
+  if (staging) {
+    g.unlock();
+    bool ok = true;
+    for (uint32_t i = 0; i < n_in; ++i)
+      if (staged[i].bytes &&
+          hipMemcpy((void*)(uintptr_t)staged[i].addr, in[i].data, staged[i].bytes,
+                    hipMemcpyHostToDevice) != hipSuccess)
+        ok = false;
+    g.lock();
+    if (!ok) {
+      release_all();
+      return CAF_E_DEVICE;
+    }
+    if (!s->actors[aidx].alive || s->shut) {
+      release_all();
+      return CAF_E_NO_ACTOR;
     }
   }
   d.in0 = inptr[0];
@@ -578,11 +665,10 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   d.out = stage_out[0];
   for (uint32_t h = 0; h < nhops; ++h) d.hop_out[h] = stage_out[h + 1];
 
+  // ---- register the request and enqueue it in call order ---------------
   caf_future* f = nullptr;
   if (is_request) {
-    f = new caf_future();
-    f->sys = s;
-    f->out = out_blk;
+    f = new_future(s);
     f->result.dtype = final_shape.dtype;
     f->result.numel = final_shape.numel;
     if (inline_out) {
@@ -592,75 +678,78 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
       f->result.data = (void*)(uintptr_t)stage_out[nhops];
       f->result.on_device = 1;
     }
+    if (!user_out) f->out = sout[nhops];
+    f->q = q;
+    f->tag = tag;
   }
-
-  // Enqueue in call order: the mailbox is FIFO per (sender, actor).
-  {
-    std::lock_guard<std::mutex> g(s->mu);
-    ActorRec& ar = s->actors[aidx];
-    if (!ar.alive) {
-      for (auto& b : blocks) s->arena.free(b.addr, b.bytes);
-      s->free_slots.push_back(slot);
-      if (f) {
-        if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
-        delete f;
-      }
-      return CAF_E_NO_ACTOR;
-    }
-    const uint64_t rid = (s->req_seq++ << kSlotBits) | slot;
-    d.req_id = rid;
-    d.slot = slot;
-    d.seq = ar.seq++;
-    SlotInfo& si = s->slots[slot];
-    si.req_id = rid;
-    si.fut = f;
-    si.temps = std::move(blocks);
-    if (f) {
-      f->req_id = rid;
-      f->t_issue = now_ns();
-    }
-    s->outstanding.fetch_add(1);
-    if (is_request) s->st_requests++;
-    else s->st_sends++;
-    if (s->cfg.mode == CAF_MODE_PLAIN) {
-      // One launch per stage; stages of a pipeline follow in stream order.
-      for (uint32_t k = 0; k <= nhops; ++k) {
-        Desc sd = d;
-        if (k > 0) {
-          const Shape& ps = k == 1 ? sh : hsh[k - 2];
-          sd.actor = hidx[k - 1];
-          sd.behavior = (uint16_t)hop[k - 1].behavior;
-          sd.in0 = stage_out[k - 1];
-          sd.in1 = 0;
-          sd.out = stage_out[k];
-          std::memset(sd.p.raw, 0, sizeof sd.p.raw);
-          sd.p.s.rows = ps.rows;
-          sd.p.s.cols = ps.cols;
-          sd.flags = (uint16_t)(d.flags & DF_SEND);
-          sd.tcfg = 0;
-          sd.seq = s->actors[hidx[k - 1]].seq++;
-        }
-        sd.hop_actor[0] = sd.hop_actor[1] = 0;
-        if (k < nhops) sd.flags |= DF_NO_COMPLETE;
-        hipError_t e = launch_plain(s->kargs, sd, desc_ntiles(sd), s->stream);
-        s->st_launches++;
-        if (e != hipSuccess) {
-          std::fprintf(stderr, "cafgpu: launch failed: %s\n", hipGetErrorString(e));
-        }
-      }
-    } else {
-      Desc* slotp = &s->hring[s->tail % s->cap];
-      std::memcpy(slotp, &d, sizeof d);
-      s->tail += 1;
-      __atomic_store_n(&s->hctl->tail, s->tail, __ATOMIC_RELEASE);
-    }
+  const uint64_t rid = (s->req_seq++ << kSlotBits) | slot;
+  d.req_id = rid;
+  d.slot = slot;
+  d.seq = s->actors[aidx].seq++;
+  SlotInfo& si = s->slots[slot];
+  si.req_id = rid;
+  si.fut = f;
+  si.ntemps = 0;
+  for (auto& b : staged)
+    if (b.bytes) si.temps[si.ntemps++] = b;
+  for (uint32_t k = 0; k <= nhops; ++k)
+    if (sout[k].bytes && !(f && k == nhops)) si.temps[si.ntemps++] = sout[k];
+  if (f) {
+    f->req_id = rid;
+    f->t_issue = now_ns();
   }
+  s->outstanding.fetch_add(1, std::memory_order_acq_rel);
+  if (is_request) s->st_requests++;
+  else s->st_sends++;
+  if (s->cfg.mode == CAF_MODE_PLAIN) {
+    // One launch per stage; the stages of a pipeline follow in stream order.
+    for (uint32_t k = 0; k <= nhops; ++k) {
+      Desc sd = d;
+      if (k > 0) {
+        const Shape& ps = k == 1 ? sh : hsh[k - 2];
+        sd.actor = hidx[k - 1];
+        sd.behavior = (uint16_t)hbeh[k - 1];
+        sd.in0 = stage_out[k - 1];
+        sd.in1 = 0;
+        sd.out = stage_out[k];
+        std::memset(sd.p.raw, 0, sizeof sd.p.raw);
+        sd.p.s.rows = ps.rows;
+        sd.p.s.cols = ps.cols;
+        sd.flags = (uint16_t)(d.flags & DF_SEND);
+        sd.tcfg = 0;
+        sd.seq = s->actors[hidx[k - 1]].seq++;
+      }
+      sd.hop_actor[0] = sd.hop_actor[1] = 0;
+      if (k < nhops) sd.flags |= DF_NO_COMPLETE;
+      const hipError_t e = launch_plain(s->kargs, sd, desc_ntiles(sd), s->stream);
+      s->st_launches++;
+      if (e != hipSuccess) std::fprintf(stderr, "cafgpu: launch failed: %s\n", hipGetErrorString(e));
+    }
+  } else {
+    std::memcpy(&s->hring[s->tail % s->cap], &d, sizeof d);
+    s->tail += 1;
+    __atomic_store_n(&s->hctl->tail, s->tail, __ATOMIC_RELEASE);
+  }
+  g.unlock();
   if (s->cfg.mode != CAF_MODE_PLAIN) ensure_drain(s, false);
   if (fut) *fut = f;
   return CAF_OK;
 }
 
 }  // namespace
+
+int cafgpu_request_tagged(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
+                          uint64_t args_bytes, const caf_buf* in, uint32_t n_in,
+                          const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut,
+                          DriveQ* q, uint32_t tag) {
+  if (!fut) return CAF_E_INVALID;
+  *fut = nullptr;
+  return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut, true,
+                q, tag);
+}
+
+int64_t cafgpu_future_issue_ns(const caf_future* f) { return f->t_issue; }
+int64_t cafgpu_future_done_ns(const caf_future* f) { return f->t_done; }
 
 extern "C" {
 
@@ -684,9 +773,13 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   const uint32_t cap = cfg->ring_slots ? cfg->ring_slots : 4096;
   const uint32_t mb = cfg->max_batch ? cfg->max_batch : 1024;
   if (cap < 2 || cap > kMaxSlots || mb > kMaxBatch) return CAF_E_INVALID;
-  const uint32_t mpx = cfg->mandel_tile_px ? cfg->mandel_tile_px : 1024;
+  // Plain launches carry one message each, so their tiles are smaller to
+  // give one launch enough workgroups.
+  const uint32_t mpx = cfg->mandel_tile_px ? cfg->mandel_tile_px
+                                           : (cfg->mode == CAF_MODE_PLAIN ? 512u : 1024u);
   if (mpx % 256 != 0 || mpx > 65536) return CAF_E_INVALID;
   if (cfg->gemm_tile != 0 && cfg->gemm_tile != 64 && cfg->gemm_tile != 128) return CAF_E_INVALID;
+  if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT) return CAF_E_INVALID;
   if (hipSetDevice(cfg->device) != hipSuccess) return CAF_E_DEVICE;
   caf_gpu_system* s = new caf_gpu_system();
   s->cfg = *cfg;
@@ -707,11 +800,13 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
     chk(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     s->own_stream = true;
   }
-  if (cfg->drain_stream) s->dstream = (hipStream_t)cfg->drain_stream;
+  if (cfg->drain_stream) s->dstream[0] = (hipStream_t)cfg->drain_stream;
   else {
-    chk(hipStreamCreateWithFlags(&s->dstream, hipStreamNonBlocking));
-    s->own_dstream = true;
+    chk(hipStreamCreateWithFlags(&s->dstream[0], hipStreamNonBlocking));
+    s->own_dstream[0] = true;
   }
+  chk(hipStreamCreateWithFlags(&s->dstream[1], hipStreamNonBlocking));
+  s->own_dstream[1] = true;
   const unsigned hflags = hipHostMallocCoherent | hipHostMallocMapped;
   chk(hipHostMalloc((void**)&s->hctl, sizeof(HostCtl), hflags));
   chk(hipHostMalloc((void**)&s->hring, sizeof(Desc) * cap, hflags));
@@ -732,14 +827,21 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
     chk(hipDeviceSynchronize());
   }
   int rate_khz = 100000;
-  hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, cfg->device);
-  if (rate_khz <= 0) rate_khz = 100000;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, cfg->device) !=
+          hipSuccess ||
+      rate_khz <= 0)
+    rate_khz = 100000;
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
-  int occ = 1;
-  if (ok) chk(drain_occupancy(&occ));
-  if (occ < 1) occ = 1;
-  uint32_t grid = cfg->grid ? cfg->grid : (uint32_t)(cus * (occ < 2 ? occ : 2));
+  // Default grid: every workgroup resident (the kernel never needs that,
+  // but it is the most work in flight).
+  int occ_full = 1, occ_light = 1;
+  if (ok) chk(drain_occupancy(true, &occ_full));
+  if (ok) chk(drain_occupancy(false, &occ_light));
+  if (occ_full < 1) occ_full = 1;
+  if (occ_light < 1) occ_light = 1;
+  s->grid_full = cfg->grid ? cfg->grid : (uint32_t)(cus * occ_full);
+  s->grid_light = cfg->grid ? cfg->grid : (uint32_t)(cus * occ_light);
   if (!ok) {
     delete s;
     return CAF_E_DEVICE;
@@ -761,12 +863,14 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   a.ccap = cap;
   a.tcap = kTileMapCap;
   a.max_batch = mb;
-  const uint64_t idle_us = cfg->idle_exit_us ? cfg->idle_exit_us : 200000;
+  const uint64_t idle_us =
+      cfg->idle_exit_us ? cfg->idle_exit_us : (cfg->mode == CAF_MODE_BATCHED ? 50 : 200000);
   a.idle_ticks = idle_us * (uint64_t)rate_khz / 1000;
   a.wait_ticks = 2000ull * (uint64_t)rate_khz;  // 2 s
   a.exit_on_empty = cfg->mode == CAF_MODE_BATCHED ? 1u : 0u;
   a.grouping = (uint32_t)cfg->grouping;
-  a.grid = grid;
+  a.grid = s->grid_full;
+  a.full = 1;
   s->poller = std::thread(poller_main, s);
   *out = s;
   return CAF_OK;
@@ -774,9 +878,10 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
 
 int caf_gpu_spawn(caf_gpu_system* s, int32_t behavior, const caf_spawn_args* args,
                   caf_actor* out) {
-  if (!s || !out || s->shut) return CAF_E_INVALID;
+  if (!s || !out) return CAF_E_INVALID;
   if (behavior < CAF_BHV_NOOP || behavior > CAF_BHV_FAULT) return CAF_E_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
+  if (s->shut) return CAF_E_INVALID;
   if (s->actors.size() >= kMaxActors) return CAF_E_OVERLOAD;
   ActorRec a;
   a.behavior = behavior;
@@ -785,6 +890,7 @@ int caf_gpu_spawn(caf_gpu_system* s, int32_t behavior, const caf_spawn_args* arg
       (a.spawn.forward_to > s->actors.size() || !s->actors[a.spawn.forward_to - 1].alive))
     return CAF_E_INVALID;
   a.alive = true;
+  if (behavior == CAF_BHV_GEMM) s->need_full.store(true);
   const uint32_t idx = (uint32_t)s->actors.size();
   s->actors.push_back(a);
   __atomic_fetch_or(&s->hctl->alive[idx >> 5], 1u << (idx & 31), __ATOMIC_SEQ_CST);
@@ -794,7 +900,8 @@ int caf_gpu_spawn(caf_gpu_system* s, int32_t behavior, const caf_spawn_args* arg
 
 int caf_gpu_send(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
                  uint64_t args_bytes, const caf_buf* in, uint32_t n_in) {
-  return submit(s, dst, sender, args, args_bytes, in, n_in, nullptr, 0, nullptr, false);
+  return submit(s, dst, sender, args, args_bytes, in, n_in, nullptr, 0, nullptr, false, nullptr,
+                0);
 }
 
 int caf_gpu_request(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
@@ -802,7 +909,8 @@ int caf_gpu_request(caf_gpu_system* s, caf_actor dst, uint32_t sender, const voi
                     const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut) {
   if (!fut) return CAF_E_INVALID;
   *fut = nullptr;
-  return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut, true);
+  return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut, true,
+                nullptr, 0);
 }
 
 int caf_future_poll(caf_future* f, caf_buf* result, int32_t* reply_status) {
@@ -824,12 +932,13 @@ int caf_future_wait(caf_future* f, int64_t timeout_ns, caf_buf* result, int32_t*
   const int64_t t0 = now_ns();
   uint32_t spins = 0;
   for (;;) {
-    int r = caf_future_poll(f, result, reply_status);
-    if (r == 1) return f->state.load() == 2 ? CAF_E_TIMEOUT : CAF_OK;
+    if (caf_future_poll(f, result, reply_status) == 1)
+      return f->state.load(std::memory_order_acquire) == 2 ? CAF_E_TIMEOUT : CAF_OK;
     if (timeout_ns >= 0 && now_ns() - t0 >= timeout_ns) {
       int expect = 0;
       if (f->state.compare_exchange_strong(expect, 2)) {
         if (reply_status) *reply_status = CAF_E_TIMEOUT;
+        if (result) *result = caf_buf{nullptr, 0, f->result.dtype, 0};
         return CAF_E_TIMEOUT;
       }
       continue;  // resolved concurrently
@@ -870,6 +979,7 @@ int caf_gpu_drain(caf_gpu_system* s, int64_t timeout_ns) {
 
 int caf_gpu_get_stats(caf_gpu_system* s, caf_gpu_stats* o) {
   if (!s || !o) return CAF_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
   o->requests = s->st_requests;
   o->sends = s->st_sends;
   o->completions = s->st_completions;
@@ -888,7 +998,8 @@ int caf_gpu_get_stats(caf_gpu_system* s, caf_gpu_stats* o) {
 double caf_gpu_drain_kernel_ms(caf_gpu_system* s, uint64_t* launches) {
   if (!s) return -1.0;
   std::lock_guard<std::mutex> g(s->launch_mu);
-  hipStreamSynchronize(s->dstream);
+  hipStreamSynchronize(s->dstream[0]);
+  hipStreamSynchronize(s->dstream[1]);
   double total = 0.0;
   for (size_t i = 0; i < s->ev_used; ++i) {
     float ms = 0.f;
@@ -908,25 +1019,34 @@ int caf_gpu_shutdown(caf_gpu_system* s) {
   }
   s->cv_space.notify_all();
   __atomic_store_n(&s->hctl->stop, 1u, __ATOMIC_SEQ_CST);
-  hipStreamSynchronize(s->dstream);
+  hipStreamSynchronize(s->dstream[0]);
+  hipStreamSynchronize(s->dstream[1]);
   hipStreamSynchronize(s->stream);
   // Let the poller collect what the device finished, then stop it.
   const int64_t t0 = now_ns();
   while (s->outstanding.load() != 0 && now_ns() - t0 < 200000000LL) std::this_thread::yield();
   s->stop_poller = true;
   if (s->poller.joinable()) s->poller.join();
-  // Anything left never reached the device: answer it.
+  // Anything left never reached the device: answer it.  Futures the caller
+  // still holds stay readable and are freed by caf_future_release.
   for (uint32_t i = 0; i < s->cap; ++i) {
     SlotInfo& si = s->slots[i];
     if (!si.req_id) continue;
-    for (auto& b : si.temps) s->arena.free(b.addr, b.bytes);
     if (si.fut) {
       si.fut->status = CAF_E_QUIT;
       int expect = 0;
       si.fut->state.compare_exchange_strong(expect, 1);
-      put_ref(si.fut);
+      si.fut->refs.fetch_sub(1);  // the request in flight is gone
     }
     si = SlotInfo();
+  }
+  for (caf_future* f : s->all_futs) {
+    if (f->pooled || f->refs.load() <= 0) {
+      delete f;
+    } else {
+      f->sys = nullptr;
+      f->out = Block{};
+    }
   }
   for (auto& e : s->ev_pool) {
     hipEventDestroy(e.first);
@@ -941,13 +1061,10 @@ int caf_gpu_shutdown(caf_gpu_system* s) {
   hipHostFree(s->hring);
   hipHostFree(s->comp);
   if (s->own_stream) hipStreamDestroy(s->stream);
-  if (s->own_dstream) hipStreamDestroy(s->dstream);
+  for (int i = 0; i < 2; ++i)
+    if (s->own_dstream[i]) hipStreamDestroy(s->dstream[i]);
   delete s;
   return CAF_OK;
 }
 
 }  // extern "C"
-
-// Internal accessors for the load driver.
-int64_t cafgpu_future_issue_ns(const caf_future* f) { return f->t_issue; }
-int64_t cafgpu_future_done_ns(const caf_future* f) { return f->t_done; }

@@ -1,0 +1,244 @@
+"""Actor semantics of the GPU runtime, checked against the CPU oracle and the
+paper's rules (GPU).
+
+Sec. 2 / 4.3: a mailbox is FIFO with a single reader.  Sec. 5: a request has
+a unique id and exactly one reply, an error if the receiver is gone, and the
+waiter may give up after a timeout.  Sec. 4.4: inputs are passed by value.
+Sec. 4.6: the reply is the kernel's output; signatures are checked.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_07368_amd import gen
+from tests.gpu_util import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["plain", "batched", "persistent"]
+
+
+@pytest.fixture(scope="module", params=MODES)
+def sysm(request):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    assert torch.cuda.is_available()
+    s = cg.System(mode=request.param, arena_bytes=256 << 20, idle_exit_us=0)
+    yield s
+    s.shutdown()
+
+
+def slow_mandel_args(cg, rows=64):
+    """A tile entirely inside the main cardioid at max_iter 65535: every
+    pixel runs the full count (slow on purpose, ~1 ms)."""
+    return cg.caf_mandel_args(-0.4, -0.2, 0.4 / 512, 0.4 / 512, 512, 512, 0, rows, 65535, cg.F32)
+
+
+def test_fifo_hash_chain_three_senders(sysm):
+    from paper_1505_07368_amd import binding as cg
+    a = sysm.spawn(cg.BHV_HASHCHAIN)
+    g = gen.rng(5)
+    futs, xs = [], []
+    for i in range(240):
+        x = int(g.integers(0, 2 ** 62))
+        xs.append(x)
+        futs.append(sysm.request(a, cg.caf_hash_args(x), sender=int(g.integers(0, 3))))
+    state = 0
+    for x, f in zip(xs, futs):
+        state = oracle.hash_step(state, x)
+        st, v = f.result()
+        assert st == cg.OK and int(v[0]) == state
+
+
+def test_exactly_once_and_sends(sysm):
+    from paper_1505_07368_amd import binding as cg
+    before = sysm.stats()
+    e = sysm.spawn(cg.BHV_NOOP)
+    futs = []
+    for i in range(300):
+        x = np.array([i], np.int32)
+        if i % 3 == 0:
+            assert sysm.send(e, inputs=[x]) == cg.OK
+        else:
+            futs.append((i, sysm.request(e, inputs=[x])))
+    for i, f in futs:
+        st, v = f.result()
+        assert st == cg.OK and int(v[0]) == i
+    assert sysm.drain(30) == cg.OK
+    after = sysm.stats()
+    assert after["duplicate_completions"] == before["duplicate_completions"] == 0
+    assert after["sends"] - before["sends"] == 100
+    assert after["requests"] - before["requests"] == 200
+    assert after["completions"] - before["completions"] == 300
+    assert after["outstanding"] == 0
+
+
+def test_quit_answers_unstarted_requests(sysm):
+    from paper_1505_07368_amd import binding as cg
+    m = sysm.spawn(cg.BHV_MANDELBROT)
+    futs = [sysm.request(m, slow_mandel_args(cg)) for _ in range(12)]
+    assert sysm.quit(m) == cg.OK
+    statuses = [f.wait(60)[0] for f in futs]
+    assert set(statuses) <= {cg.OK, cg.E_QUIT}
+    # dequeue order is FIFO: the handled ones are a prefix
+    k = statuses.count(cg.OK)
+    assert statuses == [cg.OK] * k + [cg.E_QUIT] * (len(statuses) - k)
+    rc, f = sysm.request_raw(m, slow_mandel_args(cg))
+    assert rc == cg.E_NO_ACTOR and f is None
+    assert sysm.quit(m) == cg.E_NO_ACTOR
+    assert sysm.drain(30) == cg.OK
+    assert sysm.stats()["duplicate_completions"] == 0
+
+
+def test_timeout_then_late_reply_swallowed(sysm):
+    from paper_1505_07368_amd import binding as cg
+    m = sysm.spawn(cg.BHV_MANDELBROT)
+    before = sysm.stats()["swallowed"]
+    f = sysm.request(m, slow_mandel_args(cg, rows=256))
+    with pytest.raises(cg.CafError) as ei:
+        f.wait(1e-5)
+    assert ei.value.status == cg.E_TIMEOUT
+    assert f.poll()[1] == cg.E_TIMEOUT  # resolved once, as a timeout
+    assert sysm.drain(60) == cg.OK
+    assert f.poll()[1] == cg.E_TIMEOUT
+    assert sysm.stats()["swallowed"] == before + 1
+    f.release()
+
+
+def test_signature_mismatch_and_unknown_actor(sysm):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    g = sysm.spawn(cg.BHV_GEMM, n=16)
+    A = torch.zeros(16 * 16, dtype=torch.float32, device="cuda")
+    ok = cg.caf_gemm_args(16, cg.F32)
+    assert sysm.request_raw(g, ok, [A, A])[0] == cg.OK
+    assert sysm.request_raw(g, ok, [A.double(), A])[0] == cg.E_INVALID   # dtype
+    assert sysm.request_raw(g, ok, [A[:100], A])[0] == cg.E_INVALID      # element count
+    assert sysm.request_raw(g, ok, [A])[0] == cg.E_INVALID               # arity
+    assert sysm.request_raw(g, cg.caf_gemm_args(8, cg.F32),
+                            [A[:64], A[:64]])[0] == cg.E_INVALID         # n fixed at spawn
+    m = sysm.spawn(cg.BHV_MANDELBROT)
+    vp = gen.tiny_viewport()
+    assert sysm.request_raw(m, cg.mandel_args(vp, max_iter=0))[0] == cg.E_INVALID
+    assert sysm.request_raw(m, cg.mandel_args(vp, row0=500, rows=64))[0] == cg.E_INVALID
+    assert sysm.request_raw(999, ok, [A, A])[0] == cg.E_NO_ACTOR
+    assert sysm.drain(30) == cg.OK
+
+
+def test_inputs_unchanged_and_fault(sysm):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    n = 64
+    g = sysm.spawn(cg.BHV_GEMM)
+    A, B = gen.gemm_pair(8, n)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    st, C = sysm.request(g, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt]).result()
+    assert st == cg.OK
+    assert (At.cpu().numpy() == A).all() and (Bt.cpu().numpy() == B).all()
+    f = sysm.spawn(cg.BHV_FAULT)
+    for _ in range(2):  # the actor stays alive after a fault reply
+        st, v = sysm.request(f).result()
+        assert st == cg.E_FAULT and v is None
+
+
+def test_host_inputs_and_caller_output(sysm):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    n = 48
+    g = sysm.spawn(cg.BHV_GEMM)
+    A, B = gen.gemm_pair(9, n)
+    out = torch.full((n * n,), -1.0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    f = sysm.request(g, cg.caf_gemm_args(n, cg.F32), inputs=[A, B], out=out)  # host inputs
+    st, v = f.result()
+    assert st == cg.OK and v is None  # written into the caller's tensor
+    err = rel_fro(out.cpu().numpy().reshape(n, n), oracle.gemm(A, B))
+    assert err <= 1e-5, err
+
+
+def test_nonblocking_admission_overload():
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode="persistent", arena_bytes=64 << 20, ring_slots=2, blocking=False,
+                   idle_exit_us=20000) as s:
+        m = s.spawn(cg.BHV_MANDELBROT)
+        a = slow_mandel_args(cg, rows=512)
+        f1 = s.request(m, a)
+        f2 = s.request(m, a)
+        rc, f3 = s.request_raw(m, a)
+        assert rc == cg.E_OVERLOAD and f3 is None
+        assert f1.wait(60)[0] == cg.OK and f2.wait(60)[0] == cg.OK
+        f1.release()
+        f2.release()
+        assert s.drain(30) == cg.OK
+        assert s.stats()["rejected"] >= 1
+        f4 = s.request(m, cg.caf_mandel_args(-2, -1, 0.1, 0.1, 8, 8, 0, 8, 10, cg.F32))
+        assert f4.wait(30)[0] == cg.OK
+
+
+def test_pipeline_device_vs_host_forwarding(sysm):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    n, chains = 128, 24
+    rs = sysm.spawn(cg.BHV_ROWSUM, n=n)
+    th = sysm.spawn(cg.BHV_TANH, n=n)
+    gm = sysm.spawn(cg.BHV_GEMM, n=n)
+    inputs, outs_dev, outs_host = [], [], []
+    for c in range(chains):
+        A, B = gen.gemm_pair(100 + c, n)
+        inputs.append((A, B, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()))
+        outs_dev.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
+        outs_host.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    # device forwarding: gemm -> tanh (spawned without a target) -> rowsum
+    th2 = sysm.spawn(cg.BHV_TANH, n=n, forward_to=rs)
+    msgs = [{"actor": gm, "args": cg.caf_gemm_args(n, cg.F32), "inputs": [At, Bt], "out": o,
+             "forward_to": th2} for (_, _, At, Bt), o in zip(inputs, outs_dev)]
+    rc, lat, st, _ = sysm.drive(msgs, window=8)
+    assert rc == cg.OK and (st == cg.OK).all(), st
+    # host-mediated: the driver re-sends each reply to tanh, then rowsum
+    msgs = [{"actor": gm, "args": cg.caf_gemm_args(n, cg.F32), "inputs": [At, Bt], "out": o}
+            for (_, _, At, Bt), o in zip(inputs, outs_host)]
+    rc, lat, st, _ = sysm.drive(msgs, window=8, chain_hops=2, hop_actors=(th, rs))
+    assert rc == cg.OK and (st == cg.OK).all(), st
+    torch.cuda.synchronize()
+    for (A, B, _, _), od, oh in zip(inputs, outs_dev, outs_host):
+        ref = oracle.chain(A, B)
+        assert rel_fro(od.cpu().numpy(), ref) <= 1e-5
+        assert rel_fro(oh.cpu().numpy(), ref) <= 1e-5
+
+
+def test_batching_invariance(sysm):
+    """A message gives the same reply alone and inside a mixed batch:
+    bit-exact for Mandelbrot, identical for GEMM (same tile shape)."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    vp = gen.boundary_viewport(2, width=320, height=192, max_iter=700)
+    m = sysm.spawn(cg.BHV_MANDELBROT)
+    g = sysm.spawn(cg.BHV_GEMM)
+    n = 96
+    A, B = gen.gemm_pair(21, n)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    st, alone_m = sysm.request(m, cg.mandel_args(vp, row0=64, rows=64)).result()
+    alone_m = alone_m.cpu().numpy().copy()
+    st, alone_g = sysm.request(g, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt]).result()
+    alone_g = alone_g.cpu().numpy().copy()
+    futs = []
+    for i in range(40):
+        if i % 2:
+            futs.append(("g", sysm.request(g, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt])))
+        else:
+            futs.append(("m", sysm.request(m, cg.mandel_args(vp, row0=64, rows=64))))
+        futs.append(("x", sysm.request(m, cg.mandel_args(vp, row0=(i * 7) % 128, rows=64,
+                                                          fp=cg.F64))))
+    for kind, f in futs:
+        st, v = f.result()
+        assert st == cg.OK
+        if kind == "m":
+            assert (v.cpu().numpy() == alone_m).all()
+        elif kind == "g":
+            assert (v.cpu().numpy() == alone_g).all()
+    ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 320, 64, 64, 700)
+    assert (alone_m.reshape(64, 320) == ref).all()
