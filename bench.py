@@ -130,6 +130,195 @@ def small_leg(cg, torch, mode, kind, count, window):
         s.shutdown()
 
 
+MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15}
+
+
+def _bufs_array(cg, pairs):
+    """NP_BUF array (2 per message) for (ptrA, ptrB, numel, dtype) rows."""
+    arr = np.zeros(len(pairs) * 2, cg.NP_BUF)
+    pa = np.asarray(pairs, dtype=np.uint64)
+    arr["data"][0::2] = pa[:, 0]
+    arr["data"][1::2] = pa[:, 1]
+    arr["numel"][0::2] = pa[:, 2]
+    arr["numel"][1::2] = pa[:, 2]
+    arr["dtype"][:] = pa[0, 3] if len(pa) else 0
+    arr["on_device"][:] = 1
+    return arr
+
+
+def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3):
+    """The grouped-GEMM workload: `count` requests with n drawn from
+    {64, 128, 256, 512}, entries U(-1, 1) (bf16: rounded to nearest even),
+    every request with its own inputs resident in HBM."""
+    from paper_1505_07368_amd import gen
+    sizes = gen.gemm_sizes(seed, count).astype(np.int64)
+    nn = sizes * sizes
+    offs = np.concatenate([[0], np.cumsum(nn)[:-1]])
+    total = int(nn.sum())
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    A = torch.rand(total, generator=g, device="cuda") * 2 - 1
+    B = torch.rand(total, generator=g, device="cuda") * 2 - 1
+    code = cg.F32
+    if dtype == "bf16":
+        A, B, code = A.to(torch.bfloat16), B.to(torch.bfloat16), cg.BF16
+    esz = A.element_size()
+    flops = float((2 * sizes ** 3).sum())
+    bytes_ = float((nn * (2 * esz + 4)).sum())
+    s = cg.System(mode="batched", arena_bytes=4 << 30, ring_slots=count, max_batch=1024)
+    try:
+        a = s.spawn(cg.BHV_GEMM)
+        args = np.zeros(count, cg.NP_GEMM)
+        args["n"] = sizes
+        args["in_dtype"] = code
+        bufs = _bufs_array(cg, [(A.data_ptr() + int(o) * esz, B.data_ptr() + int(o) * esz,
+                                 int(m), code) for o, m in zip(offs, nn)])
+        msgs = np.zeros(count, cg.NP_MSG)
+        msgs["actor"] = a
+        msgs["n_in"] = 2
+        msgs["args"] = args.ctypes.data + np.arange(count, dtype=np.uint64) * args.itemsize
+        msgs["args_bytes"] = args.itemsize
+        msgs["in_"] = bufs.ctypes.data + np.arange(count, dtype=np.uint64) * 2 * bufs.itemsize
+        torch.cuda.synchronize()
+        keep = (args, bufs, A, B)
+        cg.drive_array(s, msgs, keep, window=count)  # warm-up
+        s.drain_kernel_ms()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc, lat, st, el = cg.drive_array(s, msgs, keep, window=count)
+            assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+        dt = (time.perf_counter() - t0) / reps
+        kms, nl = s.drain_kernel_ms()
+        kdt = kms * 1e-3 / reps
+        attain = float(np.maximum(2 * sizes ** 3 / MFMA_PEAK[dtype],
+                                  nn * (2 * esz + 4) / HBM_PEAK).sum())
+        return {"msgs_per_s": count / dt, "tflops": flops / dt / 1e12,
+                "kernel_tflops": flops / kdt / 1e12, "kernel_ms_per_batch": kdt * 1e3,
+                "mfma_frac": flops / kdt / MFMA_PEAK[dtype],
+                "hbm_gbs": bytes_ / kdt / 1e9, "hbm_frac": bytes_ / kdt / HBM_PEAK,
+                "attainable_ms": attain * 1e3, "frac_of_attainable": attain / kdt,
+                "flop_per_batch": flops, "bytes_per_batch": bytes_}
+    finally:
+        s.shutdown()
+
+
+def pipeline_leg(cg, torch, chains=100000, n=128, window=1024, seed=0):
+    """GEMM (n = 128, fp32) -> tanh -> row sum chains: device forwarding vs
+    host-mediated forwarding through the same actors."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    A = torch.rand(chains * n * n, generator=g, device="cuda") * 2 - 1
+    B = torch.rand(chains * n * n, generator=g, device="cuda") * 2 - 1
+    out = {}
+    for form in ("device", "host"):
+        s = cg.System(mode="persistent", arena_bytes=4 << 30, ring_slots=4096)
+        try:
+            rs = s.spawn(cg.BHV_ROWSUM, n=n)
+            th_fwd = s.spawn(cg.BHV_TANH, n=n, forward_to=rs)
+            th = s.spawn(cg.BHV_TANH, n=n)
+            gm = s.spawn(cg.BHV_GEMM, n=n)
+            args = np.zeros(1, cg.NP_GEMM)
+            args["n"] = n
+            args["in_dtype"] = cg.F32
+            idx = np.arange(chains, dtype=np.uint64)
+            bufs = np.zeros(chains * 2, cg.NP_BUF)
+            bufs["data"][0::2] = A.data_ptr() + idx * (n * n * 4)
+            bufs["data"][1::2] = B.data_ptr() + idx * (n * n * 4)
+            bufs["numel"] = n * n
+            bufs["dtype"] = cg.F32
+            bufs["on_device"] = 1
+            msgs = np.zeros(chains, cg.NP_MSG)
+            msgs["actor"] = gm
+            msgs["n_in"] = 2
+            msgs["args"] = args.ctypes.data
+            msgs["args_bytes"] = args.itemsize
+            msgs["in_"] = bufs.ctypes.data + idx * 2 * bufs.itemsize
+            if form == "device":
+                msgs["forward_to"] = th_fwd
+            torch.cuda.synchronize()
+            keep = (args, bufs)
+            hops = (th, rs) if form == "host" else ()
+            cg.drive_array(s, msgs[:2048], keep, window=window, chain_hops=len(hops),
+                           hop_actors=hops)
+            rc, lat, st, el = cg.drive_array(s, msgs, keep, window=window,
+                                             chain_hops=len(hops), hop_actors=hops)
+            assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+            p50, p99 = percentiles(lat)
+            out[form] = {"chains_per_s": chains / el, "p50_us": p50, "p99_us": p99}
+        finally:
+            s.shutdown()
+    out["device_over_host"] = round(out["device"]["chains_per_s"] / out["host"]["chains_per_s"], 2)
+    return out
+
+
+def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 << 30):
+    """Open-loop Poisson arrivals: 70 % Mandelbrot squares (64^2..512^2,
+    max_iter 256..4096, boundary viewports, fp32), 30 % fp32 GEMM with n in
+    {32..512}; admission by HBM budget and mailbox slots, non-blocking
+    (refused requests are counted); latency from the scheduled arrival."""
+    from paper_1505_07368_amd import gen
+    d = gen.serving_mix_arrays(seed, rate, duration_s)
+    cnt = d["arrival_ns"].size
+    pool = {}
+    gg = torch.Generator(device="cuda")
+    gg.manual_seed(seed)
+    for n in gen.SERVE_GEMM_N:  # eight distinct input pairs per size
+        pool[n] = [(torch.rand(n * n, generator=gg, device="cuda") * 2 - 1,
+                    torch.rand(n * n, generator=gg, device="cuda") * 2 - 1) for _ in range(8)]
+    s = cg.System(mode="persistent", arena_bytes=budget, ring_slots=ring, blocking=False)
+    try:
+        m = s.spawn(cg.BHV_MANDELBROT)
+        gm = s.spawn(cg.BHV_GEMM)
+        margs = np.zeros(cnt, cg.NP_MANDEL)
+        margs["re_min"] = d["re_min"]
+        margs["im_min"] = d["im_min"]
+        margs["step_re"] = d["step"]
+        margs["step_im"] = d["step"]
+        margs["width"] = d["side"]
+        margs["height"] = d["side"]
+        margs["rows"] = d["side"]
+        margs["max_iter"] = d["max_iter"]
+        margs["fp"] = cg.F32
+        gargs = np.zeros(cnt, cg.NP_GEMM)
+        gargs["n"] = d["gemm_n"]
+        gargs["in_dtype"] = cg.F32
+        bufs = np.zeros(cnt * 2, cg.NP_BUF)
+        pick = np.arange(cnt) % 8
+        for n in gen.SERVE_GEMM_N:
+            sel = np.nonzero((d["gemm_n"] == n) & ~d["is_mandel"])[0]
+            for k in range(8):
+                ss = sel[pick[sel] == k]
+                bufs["data"][2 * ss] = pool[n][k][0].data_ptr()
+                bufs["data"][2 * ss + 1] = pool[n][k][1].data_ptr()
+                bufs["numel"][2 * ss] = n * n
+                bufs["numel"][2 * ss + 1] = n * n
+        bufs["dtype"] = cg.F32
+        bufs["on_device"] = 1
+        idx = np.arange(cnt, dtype=np.uint64)
+        msgs = np.zeros(cnt, cg.NP_MSG)
+        ism = d["is_mandel"]
+        msgs["actor"] = np.where(ism, m, gm)
+        msgs["n_in"] = np.where(ism, 0, 2)
+        msgs["args"] = np.where(ism, margs.ctypes.data + idx * margs.itemsize,
+                                gargs.ctypes.data + idx * gargs.itemsize)
+        msgs["args_bytes"] = np.where(ism, margs.itemsize, gargs.itemsize)
+        msgs["in_"] = np.where(ism, 0, bufs.ctypes.data + idx * 2 * bufs.itemsize)
+        torch.cuda.synchronize()
+        keep = (margs, gargs, bufs, pool)
+        rc, lat, st, el = cg.drive_array(s, msgs, keep, window=ring, arrival_ns=d["arrival_ns"])
+        ok = st == cg.OK
+        rej = st == cg.E_OVERLOAD
+        assert ((st == cg.OK) | rej).all(), np.unique(st)
+        p50, p99 = percentiles(lat[ok])
+        pm50, pm99 = percentiles(lat[ok & ism])
+        return {"offered_per_s": cnt / duration_s, "messages": int(cnt),
+                "completed": int(ok.sum()), "rejected": int(rej.sum()),
+                "goodput_per_s": float(ok.sum()) / el, "elapsed_s": el,
+                "p50_us": p50, "p99_us": p99, "mandel_p50_us": pm50, "mandel_p99_us": pm99}
+    finally:
+        s.shutdown()
+
+
 def cpu_oracle_tile(args):
     import oracle
     vp, r0, rows = args
@@ -241,6 +430,16 @@ def main():
                     row["batched"]["msgs_per_s"] / row["plain"]["msgs_per_s"], 2)
                 small[f"{kind}_w{window}"] = row
         result["small_messages"] = small
+        for dt in ("f32", "bf16"):
+            log(f"[bench] gemm batch {dt}")
+            result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt)
+        log("[bench] pipeline")
+        result["pipeline"] = pipeline_leg(cg, torch)
+        serving = {}
+        for rate in (1e4, 1e5, 1e6):
+            log(f"[bench] serving {rate:g}/s")
+            serving[f"{rate:g}"] = serving_leg(cg, torch, rate)
+        result["serving"] = serving
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline()

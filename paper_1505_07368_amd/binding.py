@@ -359,6 +359,42 @@ class System:
             pass
 
 
+# numpy mirrors of the C structs, for building large message lists without
+# a Python loop (layouts are checked against the header by the tests).
+NP_BUF = np.dtype({"names": ["data", "numel", "dtype", "on_device"],
+                   "formats": [np.uint64, np.uint64, np.int32, np.uint32],
+                   "offsets": [0, 8, 16, 20], "itemsize": 24})
+NP_MSG = np.dtype({"names": ["actor", "sender", "n_in", "args", "args_bytes", "in_", "out",
+                             "forward_to"],
+                   "formats": [np.uint64, np.uint32, np.uint32, np.uint64, np.uint64, np.uint64,
+                               NP_BUF, np.uint64],
+                   "offsets": [0, 8, 12, 16, 24, 32, 40, 64], "itemsize": 72})
+NP_MANDEL = np.dtype({"names": ["re_min", "im_min", "step_re", "step_im", "width", "height",
+                                "row0", "rows", "max_iter", "fp"],
+                      "formats": [np.float64] * 4 + [np.uint32] * 5 + [np.int32],
+                      "offsets": [0, 8, 16, 24, 32, 36, 40, 44, 48, 52], "itemsize": 56})
+NP_GEMM = np.dtype({"names": ["n", "in_dtype"], "formats": [np.uint32, np.int32],
+                    "offsets": [0, 4], "itemsize": 8})
+
+
+def drive_array(system, msgs: np.ndarray, keep, window=1, arrival_ns=None, chain_hops=0,
+                hop_actors=()):
+    """caf_gpu_drive over a NP_MSG array whose pointers reference buffers
+    kept alive by `keep`.  Returns (rc, latency_ns, status, elapsed_s)."""
+    assert msgs.dtype == NP_MSG and msgs.flags.c_contiguous
+    n = msgs.size
+    lat = np.full(n, -1, np.int64)
+    st = np.full(n, E_INVALID, np.int32)
+    arrival = None if arrival_ns is None else np.ascontiguousarray(arrival_ns, np.int64)
+    hops = (C.c_uint64 * max(1, len(hop_actors)))(*hop_actors)
+    el = C.c_double()
+    rc = load().caf_gpu_drive(system.h, msgs.ctypes.data_as(C.POINTER(caf_msg)), n, window,
+                              arrival.ctypes.data if arrival is not None else None, chain_hops,
+                              hops, lat.ctypes.data, st.ctypes.data, C.byref(el))
+    del keep
+    return rc, lat, st, el.value
+
+
 def mandel_args(vp, row0=0, rows=None, fp=F32, max_iter=None) -> caf_mandel_args:
     rows = vp.height - row0 if rows is None else rows
     return caf_mandel_args(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, vp.height,

@@ -156,3 +156,24 @@ def serving_mix(seed: int, rate: float, duration_s: float, mandel_frac: float = 
             msgs.append(ServeMsg("gemm", int(t), n=int(g.choice(SERVE_GEMM_N)),
                                  seed=int(g.integers(0, 2**31))))
     return msgs
+
+
+def serving_mix_arrays(seed: int, rate: float, duration_s: float, mandel_frac: float = 0.7):
+    """Vectorised serving_mix: returns a dict of numpy arrays (arrival_ns,
+    is_mandel, side, max_iter, re_min, im_min, step, gemm_n) with the same
+    distributions (boundary viewports of the main cardioid, zoom 1 to 1e4)."""
+    g = rng(seed + 1000)
+    arr = poisson_arrivals(seed, rate, duration_s)
+    n = arr.size
+    is_m = g.uniform(size=n) < mandel_frac
+    side = g.choice(np.asarray(SQUARES), size=n)
+    mi = g.choice(np.asarray(MAX_ITERS), size=n)
+    t = g.uniform(0.0, 2.0 * math.pi, size=n)
+    u = g.uniform(0.0, 1.0, size=n)
+    c0 = np.exp(1j * t) / 2 - np.exp(2j * t) / 4
+    zoom = 10.0 ** (4.0 * u)
+    step = 3.5 / zoom / side
+    gn = g.choice(np.asarray(SERVE_GEMM_N), size=n)
+    return {"arrival_ns": arr, "is_mandel": is_m, "side": side.astype(np.uint32),
+            "max_iter": mi.astype(np.uint32), "re_min": c0.real - 0.5 * side * step,
+            "im_min": c0.imag - 0.5 * side * step, "step": step, "gemm_n": gn.astype(np.uint32)}
