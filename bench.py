@@ -54,9 +54,11 @@ def percentiles(lat_ns):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False):
+def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tune=None):
     """Runs the image workload in one delivery mode; returns a dict."""
-    s = cg.System(mode=mode, arena_bytes=1 << 30, ring_slots=4096, idle_exit_us=200000)
+    tune = tune or {}
+    s = cg.System(mode=mode, arena_bytes=1 << 30, ring_slots=4096,
+                  mandel_tile_px=tune.get("mandel_tile_px", 0), grid=tune.get("grid", 0))
     try:
         a = s.spawn(cg.BHV_MANDELBROT)
         msgs = image_messages(cg, a, seeds, fp)
@@ -146,7 +148,7 @@ def _bufs_array(cg, pairs):
     return arr
 
 
-def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3):
+def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3, tile_class=(0, 0, 0, 0)):
     """The grouped-GEMM workload: `count` requests with n drawn from
     {64, 128, 256, 512}, entries U(-1, 1) (bf16: rounded to nearest even),
     every request with its own inputs resident in HBM."""
@@ -165,7 +167,8 @@ def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3):
     esz = A.element_size()
     flops = float((2 * sizes ** 3).sum())
     bytes_ = float((nn * (2 * esz + 4)).sum())
-    s = cg.System(mode="batched", arena_bytes=4 << 30, ring_slots=count, max_batch=1024)
+    s = cg.System(mode="batched", arena_bytes=4 << 30, ring_slots=count, max_batch=1024,
+                  gemm_tile_class=tuple(tile_class))
     try:
         a = s.spawn(cg.BHV_GEMM)
         args = np.zeros(count, cg.NP_GEMM)
@@ -357,6 +360,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline leg only")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the compute-actor path runs on a single MI355X; "
@@ -368,8 +372,16 @@ def main():
     torch.cuda.init()
     seeds = list(range(8))
 
+    from paper_1505_07368_amd import autotune, gen
+    cache = os.path.join(ROOT, "paper_1505_07368_amd", "autotune_cache.json")
+    vps = [gen.boundary_viewport(sd) for sd in seeds]
+    tuned = {}
+    if not args.no_tune:
+        log("[bench] autotune (mandelbrot work tile, grid)")
+        tuned["mandel"] = autotune.tune_mandel(torch, vps, cache_path=cache)
     log("[bench] batched fp32 (headline)")
-    head = mandel_leg(cg, torch, "batched", cg.F32, args.steps, args.warmup, seeds, True)
+    head = mandel_leg(cg, torch, "batched", cg.F32, args.steps, args.warmup, seeds, True,
+                      tune=tuned.get("mandel"))
     result = {
         "metric": "GPU-actor msgs/s + Mandelbrot Giter/s; p50/p99 reply latency vs 1-launch/msg",
         "value": round(head["giter_s"], 2),
@@ -406,7 +418,8 @@ def main():
             "avg_launch_ms": round(per_launch_ms, 4)}
     if not args.quick:
         log("[bench] batched fp64")
-        f64 = mandel_leg(cg, torch, "batched", cg.F64, max(2, args.steps // 2), 1, seeds, True)
+        f64 = mandel_leg(cg, torch, "batched", cg.F64, max(2, args.steps // 2), 1, seeds, True,
+                         tune=tuned.get("mandel"))
         result["fp64"] = {k: f64[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us",
                                               "iters_per_step")}
         if f64.get("kernel_ms_total"):
@@ -415,7 +428,8 @@ def main():
                 / (f64["kernel_ms_total"] * 1e-3) / VALU_LANE_OPS, 4)
         for mode in ("persistent", "plain"):
             log(f"[bench] {mode} fp32")
-            r = mandel_leg(cg, torch, mode, cg.F32, max(2, args.steps // 2), 1, seeds)
+            r = mandel_leg(cg, torch, mode, cg.F32, max(2, args.steps // 2), 1, seeds,
+                           tune=tuned.get("mandel") if mode != "plain" else None)
             result[mode] = {k: r[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
         small = {}
         for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096)):
@@ -431,8 +445,13 @@ def main():
                 small[f"{kind}_w{window}"] = row
         result["small_messages"] = small
         for dt in ("f32", "bf16"):
+            tc = (0, 0, 0, 0)
+            if not args.no_tune:
+                log(f"[bench] autotune gemm {dt}")
+                tc = autotune.tune_gemm(torch, dtype=dt, cache_path=cache)
+                tuned[f"gemm_{dt}_tile_class"] = tc
             log(f"[bench] gemm batch {dt}")
-            result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt)
+            result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt, tile_class=tc)
         log("[bench] pipeline")
         result["pipeline"] = pipeline_leg(cg, torch)
         serving = {}
@@ -440,6 +459,7 @@ def main():
             log(f"[bench] serving {rate:g}/s")
             serving[f"{rate:g}"] = serving_leg(cg, torch, rate)
         result["serving"] = serving
+    result["tuned"] = tuned
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline()

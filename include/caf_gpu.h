@@ -126,7 +126,9 @@ typedef struct {
   int32_t grouping;      /* caf_grouping */
   uint32_t mandel_tile_px; /* pixels per Mandelbrot work tile (multiple of 256);
                               0 = 512 (plain), 1024 (batched / persistent) */
-  uint32_t gemm_tile;      /* GEMM output tile edge (64 or 128); 0 = by n */
+  uint32_t gemm_tile;      /* GEMM output tile edge (64 or 128) for every n; 0 = per class */
+  uint32_t gemm_tile_class[4]; /* tile edge for n <= 64, <= 128, <= 256, > 256;
+                                  0 = default (64 up to n = 128, else 128) */
 } caf_gpu_config;
 
 /* Parameter blocks (the non-buffer part of a message), one per behaviour. */

@@ -460,6 +460,9 @@ int check_signature(const ActorRec& a, const void* args, uint64_t args_bytes, co
 
 uint32_t gemm_tile_for(const caf_gpu_system* s, uint32_t n) {
   if (s->gemm_tile == 64 || s->gemm_tile == 128) return s->gemm_tile;
+  const uint32_t cls = n <= 64 ? 0u : n <= 128 ? 1u : n <= 256 ? 2u : 3u;
+  const uint32_t t = s->cfg.gemm_tile_class[cls];
+  if (t == 64 || t == 128) return t;
   return n <= 128 ? 64u : 128u;
 }
 
@@ -779,6 +782,8 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
                                            : (cfg->mode == CAF_MODE_PLAIN ? 512u : 1024u);
   if (mpx % 256 != 0 || mpx > 65536) return CAF_E_INVALID;
   if (cfg->gemm_tile != 0 && cfg->gemm_tile != 64 && cfg->gemm_tile != 128) return CAF_E_INVALID;
+  for (uint32_t t : cfg->gemm_tile_class)
+    if (t != 0 && t != 64 && t != 128) return CAF_E_INVALID;
   if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT) return CAF_E_INVALID;
   if (hipSetDevice(cfg->device) != hipSuccess) return CAF_E_DEVICE;
   caf_gpu_system* s = new caf_gpu_system();
