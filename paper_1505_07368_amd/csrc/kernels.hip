@@ -285,7 +285,9 @@ __device__ void run_tile(const KArgs& a, const Desc& d, uint32_t tile, uint8_t* 
   }
 }
 
-constexpr uint32_t kSmemBytes = 2 * 128 * 40 * 2;  // largest tile: bf16 GEMM, TE = 128
+// LDS of the full variant: the largest work tile, two buffers of a bf16 GEMM
+// slice at TE = 128.  The light variant only needs the drain scratch.
+constexpr uint32_t kSmemBytes = 2 * (2 * 128 * 40 * 2);
 
 // ---- one launch per message -------------------------------------------------
 
@@ -352,6 +354,7 @@ struct DrainLds {
   uint32_t total;
 };
 static_assert(sizeof(DrainLds) <= kSmemBytes, "drain scratch fits the tile LDS");
+constexpr uint32_t kSmemLight = (sizeof(DrainLds) + 15u) / 16u * 16u;
 
 // In-place exclusive prefix sum of v[0..count), count <= 1024, whole workgroup.
 __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* wave_sum) {
@@ -573,7 +576,7 @@ constexpr uint32_t kSentinels = 16;
 
 template <bool kFull>
 __device__ __forceinline__ void drain_body(const KArgs& a) {
-  __shared__ __align__(16) uint8_t smem[kSmemBytes];
+  __shared__ __align__(16) uint8_t smem[kFull ? kSmemBytes : kSmemLight];
   __shared__ __align__(16) DevSlot s_slot;
   __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop;
   __shared__ uint64_t s_g;

@@ -210,14 +210,19 @@ __device__ __forceinline__ void store_c(float* C, uint32_t n, uint32_t row_base,
   }
 }
 
-// fp32 inputs: v_mfma_f32_32x32x2f32, k slices of 16.
+// Per-thread register staging of one K slice: the next slice is loaded from
+// global memory while the matrix cores work on the current one (from the
+// other LDS buffer), so one barrier per slice suffices.
+
+// fp32 inputs: v_mfma_f32_32x32x2f32, k slices of 16; LDS A k-major
+// (transposed on store), B row-major.  smem: 2 x 2 x 16 x TE floats.
 template <int TE>
 __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restrict__ B,
                               float* __restrict__ C, uint32_t n, uint32_t tile, float* smem) {
   constexpr int BK = 16;
-  constexpr int WB = TE / 64;  // 32x32 blocks per wave and dimension
-  float* As = smem;            // [BK][TE], k-major (transposed)
-  float* Bs = smem + BK * TE;  // [BK][TE], row-major
+  constexpr int WB = TE / 64;               // 32x32 blocks per wave and dimension
+  constexpr int Q = TE * BK / 4 / kThreads; // float4 per thread and operand
+  constexpr int SLICE = 2 * BK * TE;        // floats per LDS buffer
   uint32_t tm, tn;
   tile_coords(tile, n, TE, tm, tn);
   const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -232,42 +237,7 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  for (uint32_t k0 = 0; k0 < n; k0 += BK) {
-    if (vec) {
-#pragma unroll
-      for (int q = 0; q < TE * BK / 4 / kThreads; ++q) {
-        const uint32_t idx = t + kThreads * q;
-        // A: row idx/4, k quad idx%4
-        {
-          const uint32_t row = idx >> 2, kq = (idx & 3) * 4;
-          const uint32_t gr = tm * TE + row, gk = k0 + kq;
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (gr < n && gk < n) v = *reinterpret_cast<const float4*>(A + (uint64_t)gr * n + gk);
-          As[(kq + 0) * TE + row] = v.x;
-          As[(kq + 1) * TE + row] = v.y;
-          As[(kq + 2) * TE + row] = v.z;
-          As[(kq + 3) * TE + row] = v.w;
-        }
-        // B: k row idx/(TE/4), column quad
-        {
-          const uint32_t kr = idx / (TE / 4), c = (idx % (TE / 4)) * 4;
-          const uint32_t gk = k0 + kr, gc = tn * TE + c;
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (gk < n && gc < n) v = *reinterpret_cast<const float4*>(B + (uint64_t)gk * n + gc);
-          *reinterpret_cast<float4*>(Bs + kr * TE + c) = v;
-        }
-      }
-    } else {
-      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
-        const uint32_t row = idx / BK, kk = idx % BK;
-        const uint32_t gr = tm * TE + row, gk = k0 + kk;
-        As[kk * TE + row] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : 0.f;
-        const uint32_t kr = idx / TE, c = idx % TE;
-        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        Bs[kr * TE + c] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : 0.f;
-      }
-    }
-    __syncthreads();
+  auto mfma_slice = [&](const float* As, const float* Bs) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const uint32_t kr = kk + (lane >> 5);
@@ -282,7 +252,69 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
         for (int j = 0; j < WB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+  };
+
+  if (vec) {
+    float4 ra[Q], rb[Q];
+    auto gload = [&](uint32_t k0) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const uint32_t idx = t + kThreads * q;
+        const uint32_t row = idx >> 2, kq = (idx & 3) * 4;
+        const uint32_t gr = tm * TE + row, gk = k0 + kq;
+        ra[q] = (gr < n && gk < n) ? *reinterpret_cast<const float4*>(A + (uint64_t)gr * n + gk)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint32_t kr = idx / (TE / 4), c = (idx % (TE / 4)) * 4;
+        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+        rb[q] = (gk2 < n && gc < n) ? *reinterpret_cast<const float4*>(B + (uint64_t)gk2 * n + gc)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    auto lstore = [&](float* buf) {
+      float* As = buf;
+      float* Bs = buf + BK * TE;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const uint32_t idx = t + kThreads * q;
+        const uint32_t row = idx >> 2, kq = (idx & 3) * 4;
+        As[(kq + 0) * TE + row] = ra[q].x;
+        As[(kq + 1) * TE + row] = ra[q].y;
+        As[(kq + 2) * TE + row] = ra[q].z;
+        As[(kq + 3) * TE + row] = ra[q].w;
+        const uint32_t kr = idx / (TE / 4), c = (idx % (TE / 4)) * 4;
+        *reinterpret_cast<float4*>(Bs + kr * TE + c) = rb[q];
+      }
+    };
+    gload(0);
+    lstore(smem);
     __syncthreads();
+    uint32_t cur = 0;
+    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+      const bool more = k0 + BK < n;
+      if (more) gload(k0 + BK);
+      const float* buf = smem + cur * SLICE;
+      mfma_slice(buf, buf + BK * TE);
+      if (more) lstore(smem + (cur ^ 1u) * SLICE);
+      __syncthreads();
+      cur ^= 1u;
+    }
+  } else {
+    // ragged or unaligned operands: element loads, one buffer
+    float* As = smem;
+    float* Bs = smem + BK * TE;
+    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
+        const uint32_t row = idx / BK, kk = idx % BK;
+        const uint32_t gr = tm * TE + row, gk = k0 + kk;
+        As[kk * TE + row] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : 0.f;
+        const uint32_t kr = idx / TE, c = idx % TE;
+        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+        Bs[kr * TE + c] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : 0.f;
+      }
+      __syncthreads();
+      mfma_slice(As, Bs);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < WB; ++i)
@@ -295,7 +327,9 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
 // bfloat16 inputs: v_mfma_f32_32x32x16_bf16, k slices of 32.  Both operands
 // are kept k-contiguous in LDS ([row][k] for A, [column][k] for B, rows
 // padded to 80 bytes) so each lane reads its 8 k values with one 16-byte
-// LDS load.
+// LDS load.  B is transposed on the way in: a thread loads an 8 (k) x 8 (n)
+// block as eight 16-byte rows and regroups it in registers with byte
+// permutes into eight 16-byte columns.  smem: 2 x 2 x TE x 40 bf16.
 template <int TE>
 __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
                                float* __restrict__ C, uint32_t n, uint32_t tile,
@@ -303,8 +337,9 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
   constexpr int BK = 32;
   constexpr int LD = BK + 8;
   constexpr int WB = TE / 64;
-  uint16_t* As = smem;            // [TE][LD]
-  uint16_t* Bs = smem + TE * LD;  // [TE][LD] (transposed B)
+  constexpr int QA = TE * BK / 8 / kThreads;  // 16-byte A chunks per thread
+  constexpr int NBB = (BK / 8) * (TE / 8);    // 8x8 B blocks per slice
+  constexpr int SLICE = 2 * TE * LD;          // bf16 per LDS buffer
   uint32_t tm, tn;
   tile_coords(tile, n, TE, tm, tn);
   const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
@@ -319,42 +354,7 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  for (uint32_t k0 = 0; k0 < n; k0 += BK) {
-    if (vec) {
-#pragma unroll
-      for (int q = 0; q < TE * BK / 8 / kThreads; ++q) {
-        const uint32_t idx = t + kThreads * q;
-        {  // A chunk: row idx/4, 8 k values
-          const uint32_t row = idx >> 2, kc = (idx & 3) * 8;
-          const uint32_t gr = tm * TE + row, gk = k0 + kc;
-          uint4 v = make_uint4(0, 0, 0, 0);
-          if (gr < n && gk < n) v = *reinterpret_cast<const uint4*>(A + (uint64_t)gr * n + gk);
-          *reinterpret_cast<uint4*>(As + row * LD + kc) = v;
-        }
-        {  // B chunk: k row idx/(TE/8), 8 columns -> transposed store
-          const uint32_t kr = idx / (TE / 8), c = (idx % (TE / 8)) * 8;
-          const uint32_t gk = k0 + kr, gc = tn * TE + c;
-          uint4 v = make_uint4(0, 0, 0, 0);
-          if (gk < n && gc < n) v = *reinterpret_cast<const uint4*>(B + (uint64_t)gk * n + gc);
-          const uint32_t e[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-          for (int q2 = 0; q2 < 4; ++q2) {
-            Bs[(c + 2 * q2) * LD + kr] = (uint16_t)(e[q2] & 0xFFFFu);
-            Bs[(c + 2 * q2 + 1) * LD + kr] = (uint16_t)(e[q2] >> 16);
-          }
-        }
-      }
-    } else {
-      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
-        const uint32_t row = idx / BK, kk = idx % BK;
-        const uint32_t gr = tm * TE + row, gk = k0 + kk;
-        As[row * LD + kk] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : (uint16_t)0;
-        const uint32_t kr = idx / TE, c = idx % TE;
-        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        Bs[c * LD + kr] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : (uint16_t)0;
-      }
-    }
-    __syncthreads();
+  auto mfma_slice = [&](const uint16_t* As, const uint16_t* Bs) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       const uint32_t kc = ks + 8 * (lane >> 5);
@@ -375,7 +375,90 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
         for (int j = 0; j < WB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+  };
+
+  if (vec) {
+    uint4 ra[QA];
+    uint4 rb[8];  // one 8x8 block of B (threads t < NBB)
+    // k-block index fastest: neighbouring lanes write different 16-byte
+    // chunks of one LDS row pair instead of rows 8 apart (same banks)
+    const uint32_t kb = t % (BK / 8), nb = t / (BK / 8);
+    auto gload = [&](uint32_t k0) {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const uint32_t idx = t + kThreads * q;
+        const uint32_t row = idx >> 2, kc = (idx & 3) * 8;
+        const uint32_t gr = tm * TE + row, gk = k0 + kc;
+        ra[q] = (gr < n && gk < n) ? *reinterpret_cast<const uint4*>(A + (uint64_t)gr * n + gk)
+                                   : make_uint4(0, 0, 0, 0);
+      }
+      if (t < (uint32_t)NBB) {
+        const uint32_t gc = tn * TE + nb * 8;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const uint32_t gk = k0 + kb * 8 + r;
+          rb[r] = (gk < n && gc < n)
+                      ? *reinterpret_cast<const uint4*>(B + (uint64_t)gk * n + gc)
+                      : make_uint4(0, 0, 0, 0);
+        }
+      }
+    };
+    auto lstore = [&](uint16_t* buf) {
+      uint16_t* As = buf;
+      uint16_t* Bs = buf + TE * LD;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const uint32_t idx = t + kThreads * q;
+        const uint32_t row = idx >> 2, kc = (idx & 3) * 8;
+        *reinterpret_cast<uint4*>(As + row * LD + kc) = ra[q];
+      }
+      if (t < (uint32_t)NBB) {
+        // column c of the block: k pairs (2m, 2m+1) from rows 2m and 2m+1,
+        // low halves for even c, high halves for odd c
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          uint32_t col[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const uint4 lo = rb[2 * m], hi = rb[2 * m + 1];
+            const uint32_t wl = (c >> 1) == 0 ? lo.x : (c >> 1) == 1 ? lo.y : (c >> 1) == 2 ? lo.z : lo.w;
+            const uint32_t wh = (c >> 1) == 0 ? hi.x : (c >> 1) == 1 ? hi.y : (c >> 1) == 2 ? hi.z : hi.w;
+            col[m] = __builtin_amdgcn_perm(wh, wl, (c & 1) ? 0x07060302u : 0x05040100u);
+          }
+          *reinterpret_cast<uint4*>(Bs + (nb * 8 + c) * LD + kb * 8) =
+              make_uint4(col[0], col[1], col[2], col[3]);
+        }
+      }
+    };
+    gload(0);
+    lstore(smem);
     __syncthreads();
+    uint32_t cur = 0;
+    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+      const bool more = k0 + BK < n;
+      if (more) gload(k0 + BK);
+      const uint16_t* buf = smem + cur * SLICE;
+      mfma_slice(buf, buf + TE * LD);
+      if (more) lstore(smem + (cur ^ 1u) * SLICE);
+      __syncthreads();
+      cur ^= 1u;
+    }
+  } else {
+    uint16_t* As = smem;
+    uint16_t* Bs = smem + TE * LD;
+    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
+        const uint32_t row = idx / BK, kk = idx % BK;
+        const uint32_t gr = tm * TE + row, gk = k0 + kk;
+        As[row * LD + kk] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : (uint16_t)0;
+        const uint32_t kr = idx / TE, c = idx % TE;
+        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+        Bs[c * LD + kr] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : (uint16_t)0;
+      }
+      __syncthreads();
+      mfma_slice(As, Bs);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < WB; ++i)

@@ -1,0 +1,184 @@
+"""Parity at the benchmark workloads' full sizes (GPU).
+
+Each test runs a workload the benchmark times, through the same entry points
+and the same System configuration (delivery mode, ring, work-tile size and
+grid candidates of the autotuner), and checks sampled outputs against the
+oracle one by one, plus properties that hold for every output:
+
+  * the headline image batch: 8 boundary viewports of 1920x1080 at max_iter
+    1000, 17 row-tile messages each (the last has 56 rows), fp32 and fp64;
+  * the grouped GEMM batch: n drawn from {64, 128, 256, 512}, fp32 and bf16,
+    both output-tile edges;
+  * the serving mix: Mandelbrot squares 64^2..512^2 at max_iter 256..4096 and
+    fp32 GEMMs n = 32..512 through the non-blocking persistent system.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_07368_amd import gen
+from tests.gpu_util import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+SEEDS = list(range(8))
+
+
+def _image_batch(cg, torch, s, fp):
+    a = s.spawn(cg.BHV_MANDELBROT)
+    msgs, imgs = [], []
+    for seed in SEEDS:
+        vp = gen.boundary_viewport(seed)
+        img = torch.zeros(vp.height * vp.width, dtype=torch.uint16, device="cuda")
+        imgs.append((vp, img))
+        for r0, rows in gen.row_tiles(vp.height, 64):
+            view = img[r0 * vp.width:(r0 + rows) * vp.width]
+            msgs.append({"actor": a, "args": cg.mandel_args(vp, row0=r0, rows=rows, fp=fp),
+                         "out": view})
+    torch.cuda.synchronize()
+    rc, _, st, _ = s.drive(msgs, window=len(msgs))
+    assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+    assert len(msgs) == 136
+    return imgs
+
+
+def _check_images(imgs, fp):
+    for seed, (vp, img) in zip(SEEDS, imgs):
+        host = img.cpu().numpy().reshape(vp.height, vp.width)
+        assert host.min() >= 1 and host.max() <= vp.max_iter
+        g = gen.rng(500 + seed)
+        rows = set(g.integers(0, vp.height, size=2).tolist()) | {0, 63, 64, 1023, 1024, 1079}
+        for y in sorted(rows):
+            ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, y,
+                                    1, vp.max_iter, fp)
+            assert (host[y] == ref[0]).all(), (seed, y, int((host[y] != ref[0]).sum()))
+
+
+@pytest.mark.parametrize("px,half_grid", [(1024, False), (2048, False), (4096, False),
+                                          (2048, True)])
+def test_headline_batch_tile_candidates(px, half_grid):
+    """Every (work tile, grid) candidate the autotuner may pick, in float."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    grid = 0
+    if half_grid:
+        grid = int(torch.cuda.get_device_properties(0).multi_processor_count * 5 * 0.5)
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=4096, mandel_tile_px=px,
+                  grid=grid)
+    try:
+        imgs = _image_batch(cg, torch, s, cg.F32)
+    finally:
+        s.shutdown()
+    _check_images(imgs, "f32")
+
+
+@pytest.mark.parametrize("mode", ["batched", "persistent", "plain"])
+def test_headline_batch_double(mode):
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    s = cg.System(mode=mode, arena_bytes=1 << 30, ring_slots=4096)
+    try:
+        imgs = _image_batch(cg, torch, s, cg.F64)
+    finally:
+        s.shutdown()
+    _check_images(imgs, "f64")
+
+
+def _gemm_batch(cg, torch, s, sizes, dtype):
+    a = s.spawn(cg.BHV_GEMM)
+    code = cg.F32 if dtype == "f32" else cg.BF16
+    msgs, io = [], []
+    for i, n in enumerate(sizes):
+        A, B = gen.gemm_pair(1000 + i, int(n), dtype)
+        if dtype == "f32":
+            At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        else:
+            At = torch.from_numpy(A.view(np.int16)).cuda().view(torch.bfloat16)
+            Bt = torch.from_numpy(B.view(np.int16)).cuda().view(torch.bfloat16)
+        C = torch.full((int(n) * int(n),), float("nan"), device="cuda")
+        io.append((A, B, C, At, Bt))
+        msgs.append({"actor": a, "args": cg.caf_gemm_args(int(n), code), "inputs": [At, Bt],
+                     "out": C})
+    torch.cuda.synchronize()
+    rc, _, st, _ = s.drive(msgs, window=len(msgs))
+    assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+    return io
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("te", [64, 128])
+def test_gemm_batch_sampled(dtype, te):
+    """A drained batch of mixed sizes with every tile edge; one message of
+    each size (n = 512 included) checked against the FP64 oracle, every
+    output checked finite."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    sizes = gen.gemm_sizes(0, 48)
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=64, max_batch=1024,
+                  gemm_tile_class=(te, te, te, te))
+    try:
+        io = _gemm_batch(cg, torch, s, sizes, dtype)
+    finally:
+        s.shutdown()
+    seen = set()
+    for n, (A, B, C, _, _) in zip(sizes, io):
+        c = C.cpu().numpy()
+        assert np.isfinite(c).all(), n
+        if int(n) in seen:
+            continue
+        seen.add(int(n))
+        err = rel_fro(c.reshape(int(n), int(n)), oracle.gemm(A, B, dtype))
+        assert err <= 1e-5, (int(n), err)
+    assert seen == {64, 128, 256, 512}
+
+
+def test_serving_mix_sampled():
+    """Serving-mix messages (closed loop, same system configuration as the
+    serving benchmark); sampled rows of each Mandelbrot square and whole
+    GEMMs against the oracle."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    d = gen.serving_mix_arrays(0, 1e4, 0.006)
+    cnt = d["arrival_ns"].size
+    assert cnt >= 30
+    s = cg.System(mode="persistent", arena_bytes=32 << 30, ring_slots=8192, blocking=False)
+    try:
+        m = s.spawn(cg.BHV_MANDELBROT)
+        gm = s.spawn(cg.BHV_GEMM)
+        msgs, cases = [], []
+        for i in range(cnt):
+            if d["is_mandel"][i]:
+                side, mi = int(d["side"][i]), int(d["max_iter"][i])
+                vp = gen.Viewport(float(d["re_min"][i]), float(d["im_min"][i]),
+                                  float(d["step"][i]), float(d["step"][i]), side, side, mi)
+                out = torch.zeros(side * side, dtype=torch.uint16, device="cuda")
+                msgs.append({"actor": m, "args": cg.mandel_args(vp), "out": out})
+                cases.append(("mandel", vp, out))
+            else:
+                n = int(d["gemm_n"][i])
+                A, B = gen.gemm_pair(2000 + i, n)
+                At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+                C = torch.full((n * n,), float("nan"), device="cuda")
+                msgs.append({"actor": gm, "args": cg.caf_gemm_args(n, cg.F32),
+                             "inputs": [At, Bt], "out": C})
+                cases.append(("gemm", (A, B, At, Bt), C))
+        torch.cuda.synchronize()
+        rc, _, st, _ = s.drive(msgs, window=len(msgs))
+        assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+    finally:
+        s.shutdown()
+    g = gen.rng(9)
+    for kind, x, out in cases:
+        if kind == "mandel":
+            vp = x
+            host = out.cpu().numpy().reshape(vp.height, vp.width)
+            assert host.min() >= 1 and host.max() <= vp.max_iter
+            for y in sorted({0, vp.height - 1, int(g.integers(0, vp.height))}):
+                ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width,
+                                        y, 1, vp.max_iter, "f32")
+                assert (host[y] == ref[0]).all(), (vp, y)
+        else:
+            A, B = x[0], x[1]
+            n = A.shape[0]
+            err = rel_fro(out.cpu().numpy().reshape(n, n), oracle.gemm(A, B))
+            assert err <= 1e-5, (n, err)
