@@ -23,6 +23,10 @@ constexpr uint32_t kTanhTile = 4096;   // elements per tanh work tile
 constexpr uint32_t kRowsumTile = 16;   // rows per row-sum work tile
 constexpr uint32_t kMandelBlockW = 16; // a wave's pixel block: 4 rows x 16 columns
 constexpr uint32_t kMandelBlockH = 4;
+// Entries of the device tile map (global tile index -> slot); a power of two
+// so the ring position is a mask.
+constexpr uint32_t kTileMapCap = 1u << 22;
+static_assert((kTileMapCap & (kTileMapCap - 1)) == 0, "tile map size is a power of two");
 
 enum DescFlags : uint16_t {
   DF_FP64 = 1,       // Mandelbrot in double (else float)
@@ -141,7 +145,7 @@ struct KArgs {
   SlotState* sstate;
   uint32_t* tile2slot;
   DevActor* actors;
-  uint32_t cap, ccap, tcap, max_batch;
+  uint32_t cap, ccap, max_batch;
   uint64_t idle_ticks;    // persistent: exit after this many wall-clock ticks idle
   uint64_t wait_ticks;    // bound of any device-side wait
   uint32_t gen;           // launch generation

@@ -47,6 +47,15 @@
 
 namespace cafgpu {
 
+// Kernel arguments are read in place from the kernarg segment (the constant
+// address space): handing the by-value parameter to an out-of-line function
+// by reference would make every lane copy it into scratch memory.  KArgs is
+// the first parameter of every kernel here, so it starts the segment.
+typedef __attribute__((address_space(4))) const KArgs KArgsC;
+__device__ __forceinline__ KArgsC& kargs() {
+  return *(KArgsC*)(__builtin_amdgcn_kernarg_segment_ptr());
+}
+
 // ---- scoped memory operations ---------------------------------------------
 
 template <typename T>
@@ -100,11 +109,11 @@ __device__ __forceinline__ bool actor_alive(const HostCtl* h, uint32_t actor) {
 // ---- completion -------------------------------------------------------------
 
 // Publishes one reply notification to the host (thread-level).
-__device__ void write_completion(const KArgs& a, uint64_t req_id, int32_t status,
+__device__ void write_completion(KArgsC& a, uint64_t req_id, int32_t status,
                                  const uint8_t* data) {
   const uint64_t pos = __hip_atomic_fetch_add(&a.dctl->comp_tail, (uint64_t)1,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  Comp* c = &a.comp[pos % a.ccap];
+  Comp* c = &a.comp[pos & (a.ccap - 1u)];  // ccap is a power of two
   st_sys(&c->req_id, req_id);
   st_sys(&c->status, status);
   uint32_t* dst = reinterpret_cast<uint32_t*>(c->data);
@@ -113,28 +122,28 @@ __device__ void write_completion(const KArgs& a, uint64_t req_id, int32_t status
     if (data) v = reinterpret_cast<const uint32_t*>(data)[i];
     st_sys(dst + i, v);
   }
-  st_sys_rel(&c->lap, (uint32_t)(pos / a.ccap) + 1u);
+  st_sys_rel(&c->lap, (uint32_t)(pos >> __builtin_ctz(a.ccap)) + 1u);
 }
 
 // Appends `nt` tiles of slot `slot` to the global tile sequence (caller
 // holds the drain lock).  Returns false if the tile map has no room within
 // the wait bound.
-__device__ bool publish_tiles_locked(const KArgs& a, uint32_t slot, uint32_t nt) {
+__device__ bool publish_tiles_locked(KArgsC& a, uint32_t slot, uint32_t nt) {
   uint64_t t0 = now_ticks();
   uint64_t pub = ld_dev_acq(&a.dctl->tiles_pub);
-  while (pub + nt > ld_dev_acq(&a.dctl->tiles_done) + a.tcap / 2) {
+  while (pub + nt > ld_dev_acq(&a.dctl->tiles_done) + kTileMapCap / 2) {
     if (now_ticks() - t0 > a.wait_ticks) return false;
     backoff_sleep(2);
   }
   a.slots[slot].tile_base = pub;
   a.slots[slot].ntiles = nt;
-  for (uint32_t t = 0; t < nt; ++t) a.tile2slot[(pub + t) % a.tcap] = slot;
+  for (uint32_t t = 0; t < nt; ++t) a.tile2slot[(pub + t) & (kTileMapCap - 1)] = slot;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   st_dev_rel(&a.dctl->tiles_pub, pub + nt);
   return true;
 }
 
-__device__ bool lock_drain(const KArgs& a, bool bounded) {
+__device__ bool lock_drain(KArgsC& a, bool bounded) {
   uint64_t t0 = now_ticks();
   for (;;) {
     uint32_t z = 0;
@@ -145,12 +154,12 @@ __device__ bool lock_drain(const KArgs& a, bool bounded) {
   }
 }
 
-__device__ void unlock_drain(const KArgs& a) { st_dev_rel(&a.dctl->drain_lock, 0u); }
+__device__ void unlock_drain(KArgsC& a) { st_dev_rel(&a.dctl->drain_lock, 0u); }
 
 // Forwards the finished reply of `d` to the next actor of its pipeline as a
 // new message in the same slot (thread-level, drain kernel only).
-CAF_RARE void forward_reply(const KArgs& a, const Desc& d) {
-  const uint32_t slot = d.slot;
+CAF_RARE void forward_reply(KArgsC& a, uint32_t slot) {
+  const Desc d = a.slots[slot].d;
   const uint32_t hop = d.hop_actor[0];
   const uint32_t actor = (hop & 0xFFFFu) - 1u;
   const uint16_t behavior = (uint16_t)(hop >> 16);
@@ -188,7 +197,7 @@ CAF_RARE void forward_reply(const KArgs& a, const Desc& d) {
 // Accounts one finished tile of message `d` (thread 0, after the
 // workgroup's tile work is complete).  The last tile of a message resets
 // the slot's counters and completes or forwards it.
-__device__ void finish_tile(const KArgs& a, const Desc& d, uint32_t ntiles, bool ring) {
+__device__ __forceinline__ void finish_tile(KArgsC& a, const Desc& d, uint32_t ntiles, bool ring) {
   const uint32_t slot = d.slot;
   SlotState* ss = &a.sstate[slot];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -200,7 +209,7 @@ __device__ void finish_tile(const KArgs& a, const Desc& d, uint32_t ntiles, bool
     st_dev(&ss->done, 0u);
     st_dev(&ss->decision, 0u);
     if (ring && st == CAF_OK && d.hop_actor[0] != 0) {
-      forward_reply(a, d);
+      forward_reply(a, slot);
     } else if (!(d.flags & DF_NO_COMPLETE)) {
       st_dev(&ss->status, 0);
       const uint8_t* data = (d.flags & DF_INLINE_OUT) ? a.slots[slot].inline_out : nullptr;
@@ -213,7 +222,7 @@ __device__ void finish_tile(const KArgs& a, const Desc& d, uint32_t ntiles, bool
 
 // ---- behaviour dispatch -----------------------------------------------------
 
-__device__ void hash_step(const KArgs& a, const Desc& d) {
+__device__ __forceinline__ void hash_step(KArgsC& a, const Desc& d) {
   if (threadIdx.x != 0) return;
   DevActor* act = &a.actors[d.actor];
   const uint64_t t0 = now_ticks();
@@ -235,7 +244,7 @@ __device__ void hash_step(const KArgs& a, const Desc& d) {
 // kFull = false compiles every behaviour except GEMM: without the matrix
 // tiles the kernel needs far fewer registers and runs more waves per SIMD.
 template <bool kFull>
-__device__ void run_tile(const KArgs& a, const Desc& d, uint32_t tile, uint8_t* smem,
+__device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile, uint8_t* smem,
                          uint32_t* lds_ctr) {
   switch (d.behavior) {
     case CAF_BHV_MANDELBROT:
@@ -292,7 +301,8 @@ constexpr uint32_t kSmemBytes = 2 * (2 * 128 * 40 * 2);
 // ---- one launch per message -------------------------------------------------
 
 template <bool kFull>
-__global__ void __launch_bounds__(kThreads) plain_kernel(KArgs a, Desc d, uint32_t ntiles) {
+__global__ void __launch_bounds__(kThreads) plain_kernel(KArgs, Desc d, uint32_t ntiles) {
+  KArgsC& a = kargs();
   __shared__ __align__(16) uint8_t smem[kSmemBytes];
   __shared__ uint32_t s_dec;
   __shared__ uint32_t s_ctr;
@@ -345,6 +355,7 @@ struct DrainLds {
   uint8_t key[kMaxBatch];
   uint8_t dead[kMaxBatch];
   uint32_t first_bad;  // light launch: first entry it cannot run
+  uint32_t any_dead;   // some entry's actor looked dead in the snapshot
   uint32_t alive[kAliveWords];
   uint32_t hist[kKeys];
   uint32_t running[kKeys];
@@ -393,12 +404,14 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
 
 // Drains one batch from the mailbox (whole workgroup; the caller holds the
 // drain lock, which is released here).  Returns true if anything was drained.
-// Kept out of line so its registers do not add to the tile loop's.
-CAF_RARE bool drain_once(const KArgs& a, DrainLds& L) {
+__device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
   const uint32_t t = threadIdx.x;
-  // One PCIe round trip: the ring tail, the stop flag and the actors' alive
-  // bits are read together.
+  // One PCIe round trip: the ring tail, the stop flag and a snapshot of the
+  // actors' alive bits are read together.  The snapshot is not ordered after
+  // the tail read, so a bit the host set just before publishing an entry can
+  // be missing from it; entries that look dead are checked again below.
   if (t < kAliveWords) L.alive[t] = ld_sys(&a.hctl->alive[t]);
+  if (t == 0) L.any_dead = 0;
   if (t == 0) {
     const uint64_t tail = ld_sys_acq(&a.hctl->tail);
     const uint32_t stop = ld_sys(&a.hctl->stop);
@@ -423,18 +436,37 @@ CAF_RARE bool drain_once(const KArgs& a, DrainLds& L) {
     const uint64_t* src = reinterpret_cast<const uint64_t*>(&a.hring[(L.d + i) % a.cap]);
     Desc e;
     uint64_t* dst = reinterpret_cast<uint64_t*>(&e);
+    // In two halves, so at most 64 bytes of the entry are in flight per lane.
 #pragma unroll
-    for (int q = 0; q < 16; ++q) dst[q] = ld_sys(src + q);
+    for (int q = 0; q < 8; ++q) dst[q] = ld_sys(src + q);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = 8; q < 16; ++q) dst[q] = ld_sys(src + q);
     const bool alive = (L.alive[e.actor >> 5] >> (e.actor & 31)) & 1u;
     const uint32_t slot = e.slot;
     a.slots[slot].d = e;
     L.slot[i] = slot;
     L.nt[i] = alive ? desc_ntiles(e) : 0u;
     L.dead[i] = alive ? 0 : 1;
+    if (!alive) L.any_dead = 1;
     L.key[i] = (uint8_t)(a.grouping == CAF_GROUP_LPT ? group_key(e) : 0u);
     if (!a.full && e.behavior == CAF_BHV_GEMM) atomicMin(&L.first_bad, i);
   }
   __syncthreads();
+  if (L.any_dead) {
+    // Re-read the alive word of each entry that looked dead; this read is
+    // issued after the tail acquire (the barrier above orders it), so a
+    // spawn that happened before the entry was published is visible.
+    for (uint32_t i = t; i < cnt; i += kThreads) {
+      if (!L.dead[i]) continue;
+      const Desc& e = a.slots[L.slot[i]].d;
+      if ((ld_sys(&a.hctl->alive[e.actor >> 5]) >> (e.actor & 31)) & 1u) {
+        L.dead[i] = 0;
+        L.nt[i] = desc_ntiles(e);
+      }
+    }
+    __syncthreads();
+  }
   if (L.first_bad < cnt) {
     // A light launch drains only the entries before the first GEMM message
     // and, if that is the head of the mailbox, retires so that the host
@@ -449,11 +481,11 @@ CAF_RARE bool drain_once(const KArgs& a, DrainLds& L) {
       return false;
     }
   }
-  // Flow control: keep the tile map ahead of the slowest reader by tcap/2.
+  // Flow control: keep the tile map ahead of the slowest reader by half its size.
   for (uint32_t i = t; i < cnt; i += kThreads) L.scan[i] = L.nt[i];
   __syncthreads();
   uint32_t total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
-  const uint64_t room = a.tcap / 2 - (L.pub - L.done);
+  const uint64_t room = kTileMapCap / 2 - (L.pub - L.done);
   if (total > room) {
     if (t == 0) {
       uint32_t c = 0;
@@ -517,7 +549,7 @@ CAF_RARE bool drain_once(const KArgs& a, DrainLds& L) {
     const uint64_t base = pub + L.scan[L.pos[i]];
     a.slots[slot].tile_base = base;
     a.slots[slot].ntiles = nt;
-    for (uint32_t k = 0; k < nt; ++k) a.tile2slot[(base + k) % a.tcap] = slot;
+    for (uint32_t k = 0; k < nt; ++k) a.tile2slot[(base + k) & (kTileMapCap - 1)] = slot;
     if (L.dead[i]) write_completion(a, a.slots[slot].d.req_id, CAF_E_QUIT, nullptr);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -529,6 +561,17 @@ CAF_RARE bool drain_once(const KArgs& a, DrainLds& L) {
     unlock_drain(a);
   }
   return true;
+}
+
+// The full variant keeps the drain out of line (its tile loop already needs
+// most registers); the light variant inlines it, so that the whole kernel is
+// allocated under its five-waves-per-SIMD register budget.
+CAF_RARE bool drain_once_outlined(KArgsC& a, DrainLds& L) { return drain_once_body(a, L); }
+
+template <bool kFull>
+__device__ __forceinline__ bool drain_once(KArgsC& a, DrainLds& L) {
+  if constexpr (kFull) return drain_once_outlined(a, L);
+  else return drain_once_body(a, L);
 }
 
 // ---- claiming work tiles ----------------------------------------------
@@ -548,13 +591,13 @@ struct Claim {
   uint64_t next = 0, end = 0;  // tiles [next, end) are this workgroup's
 };
 
-__device__ __forceinline__ void reserve(const KArgs& a, Claim& c) {
+__device__ __forceinline__ void reserve(KArgsC& a, Claim& c) {
   const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
   const uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
   if (cur >= pub) return;
   // guided self-scheduling: large chunks while plenty is published
-  uint64_t k = (pub - cur) / (2ull * a.grid);
-  k = k < 1 ? 1 : k > 8 ? 8 : k;
+  const uint64_t avail = pub - cur, g2 = 2ull * a.grid;
+  const uint64_t k = avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4 : avail >= 2 * g2 ? 2 : 1;
   c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   c.end = c.next + k;
@@ -562,11 +605,11 @@ __device__ __forceinline__ void reserve(const KArgs& a, Claim& c) {
 
 // Publishes filler tiles for every reserved but unpublished index (caller
 // holds the drain lock).
-__device__ void fill_reservations_locked(const KArgs& a) {
+__device__ void fill_reservations_locked(KArgsC& a) {
   const uint64_t pub = ld_dev_acq(&a.dctl->tiles_pub);
   const uint64_t cl = ld_dev(&a.dctl->tiles_claimed);
   if (cl <= pub) return;
-  for (uint64_t i = pub; i < cl; ++i) a.tile2slot[i % a.tcap] = kNopTile;
+  for (uint64_t i = pub; i < cl; ++i) a.tile2slot[i & (kTileMapCap - 1)] = kNopTile;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   st_dev_rel(&a.dctl->tiles_pub, cl);
 }
@@ -575,7 +618,7 @@ enum : uint32_t { CMD_IDLE = 0, CMD_TILE = 1, CMD_DRAIN = 2 };
 constexpr uint32_t kSentinels = 16;
 
 template <bool kFull>
-__device__ __forceinline__ void drain_body(const KArgs& a) {
+__device__ __forceinline__ void drain_body(KArgsC& a) {
   __shared__ __align__(16) uint8_t smem[kFull ? kSmemBytes : kSmemLight];
   __shared__ __align__(16) DevSlot s_slot;
   __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop;
@@ -610,7 +653,7 @@ __device__ __forceinline__ void drain_body(const KArgs& a) {
       for (uint32_t j = 0; j < nk; ++j) {
         const uint64_t g = g0 + j;
         if (t == 0) {
-          const uint32_t slot = ld_dev(&a.tile2slot[g % a.tcap]);
+          const uint32_t slot = ld_dev(&a.tile2slot[g & (kTileMapCap - 1)]);
           s_nop = slot == kNopTile;
           if (!s_nop) s_slot = a.slots[slot];
         }
@@ -644,7 +687,7 @@ __device__ __forceinline__ void drain_body(const KArgs& a) {
       continue;
     }
     if (cmd == CMD_DRAIN) {
-      const bool got = drain_once(a, *reinterpret_cast<DrainLds*>(smem));
+      const bool got = drain_once<kFull>(a, *reinterpret_cast<DrainLds*>(smem));
       __syncthreads();
       if (got) {
         last_work = now_ticks();
@@ -704,12 +747,12 @@ __device__ __forceinline__ void drain_body(const KArgs& a) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) drain_kernel_full(KArgs a) { drain_body<true>(a); }
+__global__ void __launch_bounds__(kThreads) drain_kernel_full(KArgs) { drain_body<true>(kargs()); }
 
 // The light variant asks for five waves per SIMD (at most 96 registers).
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
-drain_kernel_light(KArgs a) {
-  drain_body<false>(a);
+drain_kernel_light(KArgs) {
+  drain_body<false>(kargs());
 }
 
 // ---- host-side launch wrappers ------------------------------------------

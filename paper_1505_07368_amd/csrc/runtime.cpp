@@ -41,7 +41,6 @@ using namespace cafgpu;
 namespace {
 
 constexpr uint64_t kGranule = 256;
-constexpr uint32_t kTileMapCap = 1u << 22;
 constexpr uint32_t kMaxTemps = 6;
 constexpr uint32_t kPollBatch = 256;
 
@@ -209,6 +208,7 @@ struct caf_gpu_system {
   std::thread poller;
   std::atomic<bool> stop_poller{false};
   uint64_t comp_head = 0;
+  uint32_t ccap = 0;  // completion ring entries (power of two)
   std::atomic<uint64_t> st_requests{0}, st_sends{0}, st_completions{0}, st_launches{0},
       st_drain_launches{0}, st_dup{0}, st_swallowed{0}, st_rejected{0};
   uint32_t mandel_tile_px = 1024;
@@ -359,12 +359,12 @@ void resolve_batch(caf_gpu_system* s, const Comp* recs, uint32_t n) {
 void poller_main(caf_gpu_system* s) {
   hipSetDevice(s->device);
   uint32_t idle = 0;
-  const uint32_t ccap = s->cap;
+  const uint32_t ccap = s->ccap;
   Comp batch[kPollBatch];
   while (!s->stop_poller.load(std::memory_order_relaxed)) {
     uint32_t n = 0;
     while (n < kPollBatch) {
-      const Comp* c = &s->comp[s->comp_head % ccap];
+      const Comp* c = &s->comp[s->comp_head & (ccap - 1)];
       const uint32_t lap = (uint32_t)(s->comp_head / ccap) + 1;
       if (__atomic_load_n(&c->lap, __ATOMIC_ACQUIRE) != lap) break;
       std::memcpy(&batch[n], c, sizeof(Comp));
@@ -815,7 +815,11 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   const unsigned hflags = hipHostMallocCoherent | hipHostMallocMapped;
   chk(hipHostMalloc((void**)&s->hctl, sizeof(HostCtl), hflags));
   chk(hipHostMalloc((void**)&s->hring, sizeof(Desc) * cap, hflags));
-  chk(hipHostMalloc((void**)&s->comp, sizeof(Comp) * cap, hflags));
+  // Completion ring: a power of two >= the slot count (at most one
+  // unconsumed record per slot), so the device indexes it with a mask.
+  s->ccap = 1;
+  while (s->ccap < cap) s->ccap <<= 1;
+  chk(hipHostMalloc((void**)&s->comp, sizeof(Comp) * s->ccap, hflags));
   chk(hipMalloc((void**)&s->dctl, sizeof(DevCtl)));
   chk(hipMalloc((void**)&s->dslots, sizeof(DevSlot) * cap));
   chk(hipMalloc((void**)&s->sstate, sizeof(SlotState) * cap));
@@ -824,7 +828,7 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   if (ok) {
     std::memset(s->hctl, 0, sizeof(HostCtl));
     std::memset(s->hring, 0, sizeof(Desc) * cap);
-    std::memset(s->comp, 0, sizeof(Comp) * cap);
+    std::memset(s->comp, 0, sizeof(Comp) * s->ccap);
     chk(hipMemset(s->dctl, 0, sizeof(DevCtl)));
     chk(hipMemset(s->dslots, 0, sizeof(DevSlot) * cap));
     chk(hipMemset(s->sstate, 0, sizeof(SlotState) * cap));
@@ -865,8 +869,7 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   a.tile2slot = s->tile2slot;
   a.actors = s->dactors;
   a.cap = cap;
-  a.ccap = cap;
-  a.tcap = kTileMapCap;
+  a.ccap = s->ccap;
   a.max_batch = mb;
   const uint64_t idle_us =
       cfg->idle_exit_us ? cfg->idle_exit_us : (cfg->mode == CAF_MODE_BATCHED ? 50 : 200000);

@@ -79,12 +79,14 @@ __device__ __forceinline__ void escape_count2(T cr0, T ci0, T cr1, T ci1, uint32
                                               bool v0, bool v1, uint32_t& n0, uint32_t& n1) {
   uint64_t l0 = __builtin_amdgcn_ballot_w64(v0);
   uint64_t l1 = __builtin_amdgcn_ballot_w64(v1);
-  n0 = max_iter;
-  n1 = max_iter;
+  const uint32_t lim = __builtin_amdgcn_readfirstlane(max_iter);
+  n0 = lim;
+  n1 = lim;
   T ar = T(0), ai = T(0), br = T(0), bi = T(0);
   uint32_t it = 0;
-  if (max_iter == 0 || (l0 | l1) == 0) return;
-  do {
+  if (lim == 0 || (l0 | l1) == 0) return;
+  // One iteration of both pixels; false once the wave is done.
+  auto step = [&]() __attribute__((always_inline)) -> bool {
     T ar2 = ar * ar;
     T ai2 = ai * ai;
     T am = ar2 + ai2;
@@ -96,8 +98,8 @@ __device__ __forceinline__ void escape_count2(T cr0, T ci0, T cr1, T ci1, uint32
     const uint64_t E1 = __builtin_amdgcn_ballot_w64(e1) & l1;
     if (__builtin_expect((E0 | E1) != 0, 0)) {
       asm volatile("" ::: "memory");
-      if (e0 && n0 == max_iter) n0 = it;
-      if (e1 && n1 == max_iter) n1 = it;
+      if (e0 && n0 == lim) n0 = it;
+      if (e1 && n1 == lim) n1 = it;
       l0 &= ~E0;
       l1 &= ~E1;
     }
@@ -112,7 +114,12 @@ __device__ __forceinline__ void escape_count2(T cr0, T ci0, T cr1, T ci1, uint32
     T bd = br2 - bi2;
     br = bd + cr1;
     ++it;
-  } while (it < max_iter && (l0 | l1) != 0);
+    return it != lim && (l0 | l1) != 0;
+  };
+  // Two iterations per loop trip: the values of one iteration feed the next
+  // in alternating registers, without copies at the back edge.
+  while (step() && step()) {
+  }
 }
 
 template <typename T>
