@@ -27,13 +27,33 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: unpacked fp32/fp64 ops/s
-OPS_PER_ITER = 9                      # 3 mul + 5 add/sub + 1 compare per escape-time iteration
+# Vector peak: CUs x SIMDs x lanes x clock, one unpacked fp32 (or fp64) add or
+# multiply per lane per clock.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Arithmetic per escape-time iteration: 3 multiplies + 5 adds/subtracts.  The
+# |z|^2 > 4 test is a compare, not counted: an image with no divergence (every
+# pixel at max_iter) runs at the vector peak with 8 arithmetic ops per
+# iteration, so the compare does not cost an issue slot of its own.
+OPS_PER_ITER = 8
 HBM_PEAK = 8.0e12
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# rocprofv3 summary of the headline's dominant kernel (durations and counters).
+PROFILE = os.path.join(ROOT, "profiles", "drain_kernel_light_mandelbrot_8x1920x1080_i1000_f32.md")
+
+
+def measured_traffic():
+    """HBM bytes per drain launch from the committed counter summary, or
+    None if the device sources changed since the counters were taken."""
+    from paper_1505_07368_amd import profsum
+    kv = profsum.read_summary(PROFILE)
+    if kv.get("source_digest") != profsum.source_digest() or "traffic_bytes_per_dispatch" not in kv:
+        return None
+    return int(kv["traffic_bytes_per_dispatch"])
 
 
 def image_messages(cg, actor, seeds, fp):
@@ -55,7 +75,13 @@ def percentiles(lat_ns):
 
 
 def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tune=None):
-    """Runs the image workload in one delivery mode; returns a dict."""
+    """Runs the image workload in one delivery mode; returns a dict.
+
+    The timed steps are bracketed by device synchronisation, except for the
+    persistent form: its drain kernel stays resident for a long idle linger
+    by design, and a device-wide synchronize would wait for that linger, so
+    the closing synchronisation there is of the caller's stream (every reply
+    has already been received when the last step returns)."""
     tune = tune or {}
     s = cg.System(mode=mode, arena_bytes=1 << 30, ring_slots=4096,
                   mandel_tile_px=tune.get("mandel_tile_px", 0), grid=tune.get("grid", 0))
@@ -82,7 +108,10 @@ def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tu
             rc, lat, st, _ = s.drive(msgs, window=len(msgs))
             assert rc == cg.OK and (st == cg.OK).all()
             lats.append(lat)
-        torch.cuda.synchronize()
+        if mode == "persistent":
+            torch.cuda.current_stream().synchronize()
+        else:
+            torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         kms, launches = s.drain_kernel_ms()
         p50, p99 = percentiles(np.concatenate(lats))
@@ -361,6 +390,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline leg only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
+    ap.add_argument("--mandel-tile-px", type=int, default=0,
+                    help="headline work tile (pixels) instead of the autotuned one")
+    ap.add_argument("--grid", type=int, default=-1,
+                    help="headline drain grid (0: all resident) instead of the autotuned one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the compute-actor path runs on a single MI355X; "
@@ -376,7 +409,9 @@ def main():
     cache = os.path.join(ROOT, "paper_1505_07368_amd", "autotune_cache.json")
     vps = [gen.boundary_viewport(sd) for sd in seeds]
     tuned = {}
-    if not args.no_tune:
+    if args.mandel_tile_px or args.grid >= 0:
+        tuned["mandel"] = {"mandel_tile_px": args.mandel_tile_px, "grid": max(0, args.grid)}
+    elif not args.no_tune:
         log("[bench] autotune (mandelbrot work tile, grid)")
         tuned["mandel"] = autotune.tune_mandel(torch, vps, cache_path=cache)
     log("[bench] batched fp32 (headline)")
@@ -413,9 +448,10 @@ def main():
         result["roofline"] = {
             "bound": "alu", "achieved": round(achieved / 1e12, 3),
             "peak": round(VALU_LANE_OPS / 1e12, 3), "unit": "TFLOP/s",
-            "frac": round(achieved / VALU_LANE_OPS, 4), "traffic": None,
-            "kernel": "drain_kernel", "launches": head["kernel_launches"],
-            "avg_launch_ms": round(per_launch_ms, 4)}
+            "frac": round(achieved / VALU_LANE_OPS, 4), "traffic": measured_traffic(),
+            "kernel": "drain_kernel_light", "launches": head["kernel_launches"],
+            "avg_launch_ms": round(per_launch_ms, 4),
+            "ops_per_launch": head["iters_per_step"] * OPS_PER_ITER}
     if not args.quick:
         log("[bench] batched fp64")
         f64 = mandel_leg(cg, torch, "batched", cg.F64, max(2, args.steps // 2), 1, seeds, True,

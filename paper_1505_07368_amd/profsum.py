@@ -1,0 +1,129 @@
+"""Short text summaries of rocprofv3 output for one kernel.
+
+  python -m paper_1505_07368_amd.profsum --kernel drain_kernel_light \\
+      --trace T/bench_kernel_trace.csv --last 10 \\
+      --fetch F/bench_counter_collection.csv --write W/bench_counter_collection.csv \\
+      --copy-fetch CF/copy_counter_collection.csv --copy-write CW/copy_counter_collection.csv \\
+      --copy-kernel neg_kernel --copy-bytes 1073741824 --command "..." ...
+
+prints a markdown summary: per-dispatch durations of the kernel from a
+--kernel-trace run, and its HBM traffic per dispatch from two --pmc runs
+(FETCH_SIZE, WRITE_SIZE, in KiB per dispatch).  Each counter is scaled by what
+it reads for a copy kernel of known size (bytes read = bytes written =
+--copy-bytes per dispatch), since the counters need not count every byte
+once.  The summary ends with machine-readable `key: value` lines, including a
+digest of the kernel sources, so a reader can tell whether the figures still
+describe the code.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "tiles.h",
+                                                          "caf_internal.h")]
+
+
+def source_digest() -> str:
+    """sha256 over the device-code sources, in a fixed order."""
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def dispatch_durations_ns(trace_csv: str, kernel: str) -> list[int]:
+    """End - start of every dispatch of `kernel` (substring of the name), in
+    dispatch order."""
+    rows = [r for r in _rows(trace_csv) if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+
+
+def counter_kib(pmc_csv: str, kernel: str, counter: str) -> list[float]:
+    rows = [r for r in _rows(pmc_csv) if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in rows]
+
+
+def read_summary(path: str) -> dict:
+    """The `key: value` lines of a summary written by this module."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def _mean(v):
+    return sum(v) / len(v) if v else float("nan")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--title", default="")
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--last", type=int, default=0, help="summarise the last N dispatches only")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-kernel", default="neg_kernel")
+    ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    ap.add_argument("--pmc-last", type=int, default=0)
+    ap.add_argument("--command", action="append", default=[])
+    a = ap.parse_args(argv)
+
+    dur = dispatch_durations_ns(a.trace, a.kernel)
+    sel = dur[-a.last:] if a.last else dur
+    lines = [f"# {a.title or a.kernel}", "", "Commands (run from the repository root on the GPU; "
+             "`cd /tmp && export TMPDIR=/tmp` first):", ""]
+    lines += [f"    {c}" for c in a.command]
+    lines += ["", f"Kernel `{a.kernel}`: {len(dur)} dispatches in the trace; "
+              f"the last {len(sel)} are the timed steps.", ""]
+    lines += ["| dispatches | mean ms | min ms | max ms |", "|---|---|---|---|",
+              f"| {len(sel)} | {_mean(sel) / 1e6:.4f} | {min(sel) / 1e6:.4f} | "
+              f"{max(sel) / 1e6:.4f} |", ""]
+    kv = {"kernel": a.kernel, "source_digest": source_digest(),
+          "avg_dispatch_ms": f"{_mean(sel) / 1e6:.4f}"}
+    if a.fetch and a.write and a.copy_fetch and a.copy_write:
+        cf = _mean(counter_kib(a.copy_fetch, a.copy_kernel, "FETCH_SIZE")) * 1024.0
+        cw = _mean(counter_kib(a.copy_write, a.copy_kernel, "WRITE_SIZE")) * 1024.0
+        kf_all = counter_kib(a.fetch, a.kernel, "FETCH_SIZE")
+        kw_all = counter_kib(a.write, a.kernel, "WRITE_SIZE")
+        n = a.pmc_last
+        kf = kf_all[-n:] if n else kf_all
+        kw = kw_all[-n:] if n else kw_all
+        sf, sw = a.copy_bytes / cf, a.copy_bytes / cw
+        fb, wb = _mean(kf) * 1024.0 * sf, _mean(kw) * 1024.0 * sw
+        lines += ["HBM traffic per dispatch (counter KiB x 1024 x scale; the scale makes the "
+                  f"copy kernel read and write {a.copy_bytes / 2**30:g} GiB per dispatch):", "",
+                  "| counter | copy kernel raw bytes | scale | kernel raw KiB (mean) | "
+                  "kernel bytes (scaled) |", "|---|---|---|---|---|",
+                  f"| FETCH_SIZE | {cf:.4g} | {sf:.3f} | {_mean(kf):.1f} | {fb:.4g} |",
+                  f"| WRITE_SIZE | {cw:.4g} | {sw:.3f} | {_mean(kw):.1f} | {wb:.4g} |", ""]
+        kv.update({"fetch_scale": f"{sf:.4f}", "write_scale": f"{sw:.4f}",
+                   "fetch_bytes_per_dispatch": f"{fb:.0f}",
+                   "write_bytes_per_dispatch": f"{wb:.0f}",
+                   "traffic_bytes_per_dispatch": f"{fb + wb:.0f}"})
+    lines += ["Machine-readable:", ""] + [f"- {k}: {v}" for k, v in kv.items()]
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
