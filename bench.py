@@ -242,8 +242,12 @@ def pipeline_leg(cg, torch, chains=100000, n=128, window=1024, seed=0):
     A = torch.rand(chains * n * n, generator=g, device="cuda") * 2 - 1
     B = torch.rand(chains * n * n, generator=g, device="cuda") * 2 - 1
     out = {}
-    for form in ("device", "host"):
-        s = cg.System(mode="persistent", arena_bytes=4 << 30, ring_slots=4096)
+    # device: the drain forwards each reply on the GPU; host: the driver
+    # re-sends each reply; plain / plain_graph: one launch per stage in
+    # stream order (direct, or one replayed graph per chain).
+    for form in ("device", "host", "plain", "plain_graph"):
+        mode = form if form.startswith("plain") else "persistent"
+        s = cg.System(mode=mode, arena_bytes=4 << 30, ring_slots=4096)
         try:
             rs = s.spawn(cg.BHV_ROWSUM, n=n)
             th_fwd = s.spawn(cg.BHV_TANH, n=n, forward_to=rs)
@@ -265,7 +269,7 @@ def pipeline_leg(cg, torch, chains=100000, n=128, window=1024, seed=0):
             msgs["args"] = args.ctypes.data
             msgs["args_bytes"] = args.itemsize
             msgs["in_"] = bufs.ctypes.data + idx * 2 * bufs.itemsize
-            if form == "device":
+            if form != "host":
                 msgs["forward_to"] = th_fwd
             torch.cuda.synchronize()
             keep = (args, bufs)
@@ -280,6 +284,7 @@ def pipeline_leg(cg, torch, chains=100000, n=128, window=1024, seed=0):
         finally:
             s.shutdown()
     out["device_over_host"] = round(out["device"]["chains_per_s"] / out["host"]["chains_per_s"], 2)
+    out["device_over_plain"] = round(out["device"]["chains_per_s"] / out["plain"]["chains_per_s"], 2)
     return out
 
 
@@ -462,7 +467,7 @@ def main():
             result["fp64"]["alu_frac"] = round(
                 f64["iters_per_step"] * max(2, args.steps // 2) * OPS_PER_ITER
                 / (f64["kernel_ms_total"] * 1e-3) / VALU_LANE_OPS, 4)
-        for mode in ("persistent", "plain"):
+        for mode in ("persistent", "plain", "plain_graph"):
             log(f"[bench] {mode} fp32")
             r = mandel_leg(cg, torch, mode, cg.F32, max(2, args.steps // 2), 1, seeds,
                            tune=tuned.get("mandel") if mode != "plain" else None)
@@ -471,7 +476,7 @@ def main():
         for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096)):
             for window in ((1, 64, 1024) if kind == "echo" else (256,)):
                 row = {}
-                for mode in ("plain", "batched", "persistent"):
+                for mode in ("plain", "plain_graph", "batched", "persistent"):
                     log(f"[bench] small {kind} window {window} {mode}")
                     row[mode] = small_leg(cg, torch, mode, kind, count, window)
                 row["persistent_over_plain"] = round(

@@ -86,7 +86,14 @@ typedef enum {
   /* Messages go through the mailbox ring; a resident (persistent) drain
    * kernel polls it and exits only after idle_exit_us without work or at
    * shutdown; the library relaunches it when new work arrives. */
-  CAF_MODE_PERSISTENT = 2
+  CAF_MODE_PERSISTENT = 2,
+  /* One launch per message like CAF_MODE_PLAIN, but each message's launches
+   * (every stage of a pipeline) are replayed from an instantiated hipGraph,
+   * one per stage shape (kernel variant and tile count of each stage); the
+   * message's arguments are written into the graph's kernel nodes before
+   * each replay.  At most 64 shapes are kept; further shapes launch
+   * directly. */
+  CAF_MODE_PLAIN_GRAPH = 3
 } caf_mode;
 
 /* Order in which a drained batch's work is laid out for the workgroups. */

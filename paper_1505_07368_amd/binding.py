@@ -20,9 +20,10 @@ OK, E_INVALID, E_NO_ACTOR, E_OVERLOAD, E_TIMEOUT, E_DEVICE, E_QUIT, E_FAULT = (
     0, -1, -2, -3, -4, -5, -6, -7)
 I32, U16, F32, F64, BF16, U64 = 0, 1, 2, 3, 4, 5
 BHV_NOOP, BHV_MANDELBROT, BHV_GEMM, BHV_TANH, BHV_ROWSUM, BHV_HASHCHAIN, BHV_FAULT = range(7)
-MODE_PLAIN, MODE_BATCHED, MODE_PERSISTENT = 0, 1, 2
+MODE_PLAIN, MODE_BATCHED, MODE_PERSISTENT, MODE_PLAIN_GRAPH = 0, 1, 2, 3
 GROUP_FIFO, GROUP_LPT = 0, 1
-MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "persistent": MODE_PERSISTENT}
+MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "persistent": MODE_PERSISTENT,
+         "plain_graph": MODE_PLAIN_GRAPH}
 
 EXPORTED = ["caf_gpu_init", "caf_gpu_spawn", "caf_gpu_send", "caf_gpu_request",
             "caf_future_wait", "caf_future_poll", "caf_future_id", "caf_future_release",

@@ -156,16 +156,26 @@ __device__ bool lock_drain(KArgsC& a, bool bounded) {
 
 __device__ void unlock_drain(KArgsC& a) { st_dev_rel(&a.dctl->drain_lock, 0u); }
 
-// Forwards the finished reply of `d` to the next actor of its pipeline as a
-// new message in the same slot (thread-level, drain kernel only).
-CAF_RARE void forward_reply(KArgsC& a, uint32_t slot) {
+// Pipeline stages small enough to run where the previous stage finished:
+// the workgroup that completes a message's last tile runs the next stage
+// itself (no publication, no drain lock, no second claim) when that stage
+// has at most this many work tiles.
+constexpr uint32_t kInlineStageTiles = 16;
+
+// Forwards the finished reply in `slot` to the next actor of its pipeline:
+// the slot's descriptor becomes the next stage's (input = this reply).
+// Returns true if the caller's workgroup is to run that stage inline;
+// otherwise the stage is published for any workgroup, or (next actor gone,
+// no room) the request is completed with an error.  Thread-level, drain
+// kernel only.
+CAF_RARE bool forward_reply(KArgsC& a, uint32_t slot) {
   const Desc d = a.slots[slot].d;
   const uint32_t hop = d.hop_actor[0];
   const uint32_t actor = (hop & 0xFFFFu) - 1u;
   const uint16_t behavior = (uint16_t)(hop >> 16);
   if (!actor_alive(a.hctl, actor)) {
     write_completion(a, d.req_id, CAF_E_QUIT, nullptr);
-    return;
+    return false;
   }
   Desc nd = d;
   nd.actor = actor;
@@ -186,38 +196,52 @@ CAF_RARE void forward_reply(KArgsC& a, uint32_t slot) {
   nd.tcfg = 0;
   a.slots[slot].d = nd;
   const uint32_t nt = desc_ntiles(nd);
+  if (nt <= kInlineStageTiles) return true;
   bool ok = lock_drain(a, true);
   if (ok) {
     ok = publish_tiles_locked(a, slot, nt);
     unlock_drain(a);
   }
   if (!ok) write_completion(a, d.req_id, CAF_E_DEVICE, nullptr);
+  return false;
+}
+
+// Completes (or forwards) the message in `slot` after its current stage:
+// thread 0, once the workgroup's writes of the stage are done.  Returns true
+// if the workgroup is to run the next stage inline.
+__device__ __forceinline__ bool stage_done(KArgsC& a, const Desc& d, bool ring) {
+  const uint32_t slot = d.slot;
+  SlotState* ss = &a.sstate[slot];
+  const int32_t st = ld_dev(&ss->status);
+  if (ring && st == CAF_OK && d.hop_actor[0] != 0) return forward_reply(a, slot);
+  if (!(d.flags & DF_NO_COMPLETE)) {
+    st_dev(&ss->status, 0);
+    const uint8_t* data = (d.flags & DF_INLINE_OUT) ? a.slots[slot].inline_out : nullptr;
+    write_completion(a, d.req_id, st, data);
+  }
+  return false;
 }
 
 // Accounts one finished tile of message `d` (thread 0, after the
 // workgroup's tile work is complete).  The last tile of a message resets
-// the slot's counters and completes or forwards it.
-__device__ __forceinline__ void finish_tile(KArgsC& a, const Desc& d, uint32_t ntiles, bool ring) {
+// the slot's counters and completes or forwards it; returns true if the
+// workgroup is to run the next pipeline stage inline.
+__device__ __forceinline__ bool finish_tile(KArgsC& a, const Desc& d, uint32_t ntiles, bool ring) {
   const uint32_t slot = d.slot;
   SlotState* ss = &a.sstate[slot];
+  bool cont = false;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const uint32_t prev = __hip_atomic_fetch_add(&ss->done, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
   if (prev + 1 == ntiles) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int32_t st = ld_dev(&ss->status);
     st_dev(&ss->done, 0u);
     st_dev(&ss->decision, 0u);
-    if (ring && st == CAF_OK && d.hop_actor[0] != 0) {
-      forward_reply(a, slot);
-    } else if (!(d.flags & DF_NO_COMPLETE)) {
-      st_dev(&ss->status, 0);
-      const uint8_t* data = (d.flags & DF_INLINE_OUT) ? a.slots[slot].inline_out : nullptr;
-      write_completion(a, d.req_id, st, data);
-    }
+    cont = stage_done(a, d, ring);
   }
   if (ring) __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+  return cont;
 }
 
 // ---- behaviour dispatch -----------------------------------------------------
@@ -291,6 +315,43 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
     default:
       if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_INVALID);
       break;
+  }
+}
+
+// A pipeline stage (row-wise tanh or row sum of a float matrix) run inline
+// by the workgroup that finished the previous stage: every tile in turn.
+// `s_flag` is workgroup-shared scratch.  Whole workgroup.
+__device__ __forceinline__ void run_inline_stages(KArgsC& a, uint32_t slot, uint32_t* s_flag) {
+  for (;;) {
+    __syncthreads();
+    Desc d;
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(&a.slots[slot].d);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&d);
+#pragma unroll
+      for (int q = 0; q < (int)(sizeof(Desc) / 4); ++q)
+        dst[q] = __builtin_amdgcn_readfirstlane(src[q]);
+    }
+    const uint32_t nt = desc_ntiles(d);
+    for (uint32_t tt = 0; tt < nt; ++tt) {
+      if (ld_dev(&a.sstate[slot].status) == CAF_OK) {
+        if (d.behavior == CAF_BHV_TANH)
+          tanh_tile(reinterpret_cast<const float*>(d.in0), reinterpret_cast<float*>(d.out),
+                    (uint64_t)d.p.s.rows * d.p.s.cols, tt);
+        else if (d.behavior == CAF_BHV_ROWSUM)
+          rowsum_tile(reinterpret_cast<const float*>(d.in0), reinterpret_cast<float*>(d.out),
+                      d.p.s.rows, d.p.s.cols, tt);
+        else if (threadIdx.x == 0)
+          st_dev(&a.sstate[slot].status, (int32_t)CAF_E_INVALID);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      *s_flag = stage_done(a, d, true) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!*s_flag) break;
   }
 }
 
@@ -621,7 +682,7 @@ template <bool kFull>
 __device__ __forceinline__ void drain_body(KArgsC& a) {
   __shared__ __align__(16) uint8_t smem[kFull ? kSmemBytes : kSmemLight];
   __shared__ __align__(16) DevSlot s_slot;
-  __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop;
+  __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop, s_cont;
   __shared__ uint64_t s_g;
   const uint32_t t = threadIdx.x;
   uint64_t last_work = now_ticks();
@@ -679,8 +740,9 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         const uint32_t tile = (uint32_t)(g - s_slot.tile_base);
         if (ld_dev(&a.sstate[d.slot].status) == CAF_OK) run_tile<kFull>(a, d, tile, smem, &s_ctr);
         __syncthreads();
-        if (t == 0) finish_tile(a, d, ntiles, true);
+        if (t == 0) s_cont = finish_tile(a, d, ntiles, true) ? 1u : 0u;
         __syncthreads();
+        if (s_cont) run_inline_stages(a, d.slot, &s_cont);
       }
       last_work = now_ticks();
       idle_rounds = 0;
@@ -763,6 +825,11 @@ hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStrea
   else
     hipLaunchKernelGGL(plain_kernel<false>, dim3(ntiles), dim3(kThreads), 0, s, a, d, ntiles);
   return hipGetLastError();
+}
+
+const void* plain_kernel_fn(bool full) {
+  return full ? reinterpret_cast<const void*>(&plain_kernel<true>)
+              : reinterpret_cast<const void*>(&plain_kernel<false>);
 }
 
 hipError_t launch_drain(const KArgs& a, hipStream_t s) {

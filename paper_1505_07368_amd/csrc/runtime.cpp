@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -25,6 +26,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -34,6 +36,7 @@ namespace cafgpu {
 hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s);
 hipError_t launch_drain(const KArgs& a, hipStream_t s);
 hipError_t drain_occupancy(bool full, int* blocks_per_cu);
+const void* plain_kernel_fn(bool full);
 }  // namespace cafgpu
 
 using namespace cafgpu;
@@ -67,7 +70,7 @@ class Arena {
   }
   bool alloc(uint64_t bytes, uint64_t* addr) {
     const uint64_t need = granules(bytes);
-    auto it = by_size_.lower_bound(need);
+    auto it = by_size_.lower_bound({need, 0});
     if (it == by_size_.end()) return false;
     const uint64_t sz = it->first, off = it->second;
     erase(off, sz);
@@ -108,16 +111,11 @@ class Arena {
   }
   void erase(uint64_t off, uint64_t sz) {
     by_off_.erase(off);
-    auto r = by_size_.equal_range(sz);
-    for (auto i = r.first; i != r.second; ++i)
-      if (i->second == off) {
-        by_size_.erase(i);
-        break;
-      }
+    by_size_.erase({sz, off});
   }
   uint64_t base_ = 0, size_ = 0, in_use_ = 0, peak_ = 0;
-  std::map<uint64_t, uint64_t> by_off_;
-  std::multimap<uint64_t, uint64_t> by_size_;
+  std::map<uint64_t, uint64_t> by_off_;                 // free blocks by offset
+  std::set<std::pair<uint64_t, uint64_t>> by_size_;     // (size, offset): best fit, lowest offset
 };
 
 struct Block {
@@ -167,6 +165,16 @@ struct SlotInfo {
   uint32_t ntemps = 0;
 };
 
+// An instantiated graph of one message's plain launches (one kernel node per
+// pipeline stage, in stream order) for one stage shape.
+struct PlainGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node[1 + kMaxHops] = {};
+};
+using PlainShape = std::array<uint32_t, 2 + kMaxHops>;  // stage count, then (full << 31 | tiles)
+constexpr size_t kMaxGraphs = 64;
+
 struct caf_gpu_system {
   caf_gpu_config cfg{};
   int device = 0;
@@ -215,6 +223,8 @@ struct caf_gpu_system {
   uint32_t gemm_tile = 0;
   uint32_t grid_full = 0, grid_light = 0;  // drain-kernel workgroups per variant
   std::atomic<bool> need_full{false};       // a GEMM actor exists
+  std::map<PlainShape, PlainGraph> graphs;  // CAF_MODE_PLAIN_GRAPH, guarded by mu
+  bool plain() const { return cfg.mode == CAF_MODE_PLAIN || cfg.mode == CAF_MODE_PLAIN_GRAPH; }
 };
 
 namespace {
@@ -376,7 +386,7 @@ void poller_main(caf_gpu_system* s) {
       idle = 0;
       continue;
     }
-    if (s->cfg.mode != CAF_MODE_PLAIN && (idle & 63) == 0) ensure_drain(s, true);
+    if (!s->plain() && (idle & 63) == 0) ensure_drain(s, true);
     ++idle;
     if (idle < 20000 || s->outstanding.load(std::memory_order_relaxed) != 0) {
       _mm_pause();
@@ -525,6 +535,59 @@ void fill_desc(const caf_gpu_system* s, const ActorRec& a, uint32_t aidx, const 
   }
   if (inline_out) d->flags |= DF_INLINE_OUT;
   if (!is_request) d->flags |= DF_SEND;
+}
+
+// Replays the graph of this stage shape with the message's arguments (mu
+// held).  Returns false, launching nothing, if the shape has no graph and
+// the cache is full; *err receives the HIP status otherwise.
+bool launch_graph(caf_gpu_system* s, const Desc* sd, const uint32_t* nt, uint32_t nstages,
+                  hipError_t* err) {
+  PlainShape key{};
+  key[0] = nstages;
+  for (uint32_t k = 0; k < nstages; ++k)
+    key[1 + k] = ((sd[k].behavior == CAF_BHV_GEMM ? 1u : 0u) << 31) | nt[k];
+  auto it = s->graphs.find(key);
+  hipKernelNodeParams p[1 + kMaxHops];
+  void* argv[1 + kMaxHops][3];
+  KArgs ka = s->kargs;
+  Desc d[1 + kMaxHops];
+  uint32_t n[1 + kMaxHops];
+  for (uint32_t k = 0; k < nstages; ++k) {
+    d[k] = sd[k];
+    n[k] = nt[k];
+    argv[k][0] = &ka;
+    argv[k][1] = &d[k];
+    argv[k][2] = &n[k];
+    p[k] = hipKernelNodeParams{};
+    p[k].func = const_cast<void*>(plain_kernel_fn(sd[k].behavior == CAF_BHV_GEMM));
+    p[k].gridDim = dim3(nt[k]);
+    p[k].blockDim = dim3(kThreads);
+    p[k].sharedMemBytes = 0;
+    p[k].kernelParams = argv[k];
+    p[k].extra = nullptr;
+  }
+  hipError_t e = hipSuccess;
+  if (it == s->graphs.end()) {
+    if (s->graphs.size() >= kMaxGraphs) return false;
+    PlainGraph g;
+    e = hipGraphCreate(&g.graph, 0);
+    for (uint32_t k = 0; k < nstages && e == hipSuccess; ++k)
+      e = hipGraphAddKernelNode(&g.node[k], g.graph, k ? &g.node[k - 1] : nullptr, k ? 1 : 0,
+                                &p[k]);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (g.graph) hipGraphDestroy(g.graph);
+      *err = e;
+      return true;
+    }
+    it = s->graphs.emplace(key, g).first;
+  } else {
+    for (uint32_t k = 0; k < nstages && e == hipSuccess; ++k)
+      e = hipGraphExecKernelNodeSetParams(it->second.exec, it->second.node[k], &p[k]);
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(it->second.exec, s->stream);
+  *err = e;
+  return true;
 }
 
 int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
@@ -704,8 +767,10 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   s->outstanding.fetch_add(1, std::memory_order_acq_rel);
   if (is_request) s->st_requests++;
   else s->st_sends++;
-  if (s->cfg.mode == CAF_MODE_PLAIN) {
+  if (s->plain()) {
     // One launch per stage; the stages of a pipeline follow in stream order.
+    Desc sdesc[1 + kMaxHops];
+    uint32_t snt[1 + kMaxHops];
     for (uint32_t k = 0; k <= nhops; ++k) {
       Desc sd = d;
       if (k > 0) {
@@ -724,17 +789,23 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
       }
       sd.hop_actor[0] = sd.hop_actor[1] = 0;
       if (k < nhops) sd.flags |= DF_NO_COMPLETE;
-      const hipError_t e = launch_plain(s->kargs, sd, desc_ntiles(sd), s->stream);
-      s->st_launches++;
-      if (e != hipSuccess) std::fprintf(stderr, "cafgpu: launch failed: %s\n", hipGetErrorString(e));
+      sdesc[k] = sd;
+      snt[k] = desc_ntiles(sd);
     }
+    hipError_t e = hipSuccess;
+    if (s->cfg.mode != CAF_MODE_PLAIN_GRAPH || !launch_graph(s, sdesc, snt, nhops + 1, &e)) {
+      for (uint32_t k = 0; k <= nhops && e == hipSuccess; ++k)
+        e = launch_plain(s->kargs, sdesc[k], snt[k], s->stream);
+    }
+    s->st_launches += nhops + 1;
+    if (e != hipSuccess) std::fprintf(stderr, "cafgpu: launch failed: %s\n", hipGetErrorString(e));
   } else {
     std::memcpy(&s->hring[s->tail % s->cap], &d, sizeof d);
     s->tail += 1;
     __atomic_store_n(&s->hctl->tail, s->tail, __ATOMIC_RELEASE);
   }
   g.unlock();
-  if (s->cfg.mode != CAF_MODE_PLAIN) ensure_drain(s, false);
+  if (!s->plain()) ensure_drain(s, false);
   if (fut) *fut = f;
   return CAF_OK;
 }
@@ -772,14 +843,17 @@ const char* caf_gpu_strerror(int st) {
 
 int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   if (!cfg || !out || !cfg->arena || cfg->arena_bytes < (1u << 16)) return CAF_E_INVALID;
-  if (cfg->mode < CAF_MODE_PLAIN || cfg->mode > CAF_MODE_PERSISTENT) return CAF_E_INVALID;
+  if (cfg->mode < CAF_MODE_PLAIN || cfg->mode > CAF_MODE_PLAIN_GRAPH) return CAF_E_INVALID;
   const uint32_t cap = cfg->ring_slots ? cfg->ring_slots : 4096;
   const uint32_t mb = cfg->max_batch ? cfg->max_batch : 1024;
   if (cap < 2 || cap > kMaxSlots || mb > kMaxBatch) return CAF_E_INVALID;
   // Plain launches carry one message each, so their tiles are smaller to
   // give one launch enough workgroups.
   const uint32_t mpx = cfg->mandel_tile_px ? cfg->mandel_tile_px
-                                           : (cfg->mode == CAF_MODE_PLAIN ? 512u : 1024u);
+                                           : (cfg->mode == CAF_MODE_PLAIN ||
+                                                      cfg->mode == CAF_MODE_PLAIN_GRAPH
+                                                  ? 512u
+                                                  : 1024u);
   if (mpx % 256 != 0 || mpx > 65536) return CAF_E_INVALID;
   if (cfg->gemm_tile != 0 && cfg->gemm_tile != 64 && cfg->gemm_tile != 128) return CAF_E_INVALID;
   for (uint32_t t : cfg->gemm_tile_class)
@@ -1059,6 +1133,10 @@ int caf_gpu_shutdown(caf_gpu_system* s) {
   for (auto& e : s->ev_pool) {
     hipEventDestroy(e.first);
     hipEventDestroy(e.second);
+  }
+  for (auto& kv : s->graphs) {
+    hipGraphExecDestroy(kv.second.exec);
+    hipGraphDestroy(kv.second.graph);
   }
   hipFree(s->dctl);
   hipFree(s->dslots);

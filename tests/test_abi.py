@@ -39,6 +39,11 @@ def test_strerror_and_init_argument_checks():
     cfg = cg.caf_gpu_config()  # NULL arena: rejected before touching a device
     assert L.caf_gpu_init(C.byref(cfg), C.byref(h)) == cg.E_INVALID
     assert L.caf_gpu_init(None, C.byref(h)) == cg.E_INVALID
+    bogus = cg.caf_gpu_config()  # unknown mode: rejected before any device call
+    bogus.arena = 1 << 40
+    bogus.arena_bytes = 1 << 20
+    bogus.mode = 4
+    assert L.caf_gpu_init(C.byref(bogus), C.byref(h)) == cg.E_INVALID
     assert L.caf_gpu_spawn(None, 0, None, None) == cg.E_INVALID
     assert L.caf_gpu_quit(None, 1, 0) == cg.E_INVALID
 

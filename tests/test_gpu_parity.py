@@ -2,8 +2,9 @@
 
 Mandelbrot counts must be bit-exact in float and double; GEMM must be within
 1e-5 (fp32 inputs) / 2e-2 (bf16 inputs) relative Frobenius error of the
-float64 oracle.  Every case runs through the C ABI in each of the three
-delivery modes (one launch per message, batched drain, persistent drain).
+float64 oracle.  Every case runs through the C ABI in each of the four
+delivery modes (one launch per message, the same replayed from hipGraphs,
+batched drain, persistent drain).
 """
 import numpy as np
 import pytest
@@ -14,7 +15,7 @@ from tests.gpu_util import rel_fro
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["plain", "batched", "persistent"]
+MODES = ["plain", "plain_graph", "batched", "persistent"]
 
 
 @pytest.fixture(scope="module", params=MODES)

@@ -15,7 +15,7 @@ from tests.gpu_util import rel_fro
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["plain", "batched", "persistent"]
+MODES = ["plain", "plain_graph", "batched", "persistent"]
 
 
 @pytest.fixture(scope="module", params=MODES)
@@ -177,10 +177,13 @@ def test_nonblocking_admission_overload():
         assert f4.wait(30)[0] == cg.OK
 
 
-def test_pipeline_device_vs_host_forwarding(sysm):
+@pytest.mark.parametrize("n,chains", [(128, 24), (512, 3)])
+def test_pipeline_device_vs_host_forwarding(sysm, n, chains):
+    """n = 128: the tanh and row-sum stages are small enough to run in the
+    workgroup that finished the previous stage; n = 512: they are published
+    as work tiles for every workgroup."""
     import torch
     from paper_1505_07368_amd import binding as cg
-    n, chains = 128, 24
     rs = sysm.spawn(cg.BHV_ROWSUM, n=n)
     th = sysm.spawn(cg.BHV_TANH, n=n)
     gm = sysm.spawn(cg.BHV_GEMM, n=n)
@@ -242,3 +245,36 @@ def test_batching_invariance(sysm):
             assert (v.cpu().numpy() == alone_g).all()
     ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 320, 64, 64, 700)
     assert (alone_m.reshape(64, 320) == ref).all()
+
+
+def test_plain_graph_replays_match_oracle():
+    """CAF_MODE_PLAIN_GRAPH: one graph per stage shape, replayed with each
+    message's arguments.  Every replay is checked against the oracle, with
+    eager device work and host synchronisation between replays."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    s = cg.System(mode="plain_graph", arena_bytes=256 << 20)
+    try:
+        g = s.spawn(cg.BHV_GEMM)
+        m = s.spawn(cg.BHV_MANDELBROT)
+        vp = gen.boundary_viewport(4, width=256, height=64, max_iter=300)
+        whole = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 256, 0, 64, 300)
+        scratch = torch.ones(1 << 20, device="cuda")
+        for i in range(12):
+            A, B = gen.gemm_pair(300 + i, 64)
+            At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            torch.cuda.synchronize()
+            st, C = s.request(g, cg.caf_gemm_args(64, cg.F32), inputs=[At, Bt]).result()
+            assert st == cg.OK
+            assert rel_fro(C.cpu().numpy().reshape(64, 64), oracle.gemm(A, B)) <= 1e-5, i
+            r0 = (i * 16) % 48
+            st, img = s.request(m, cg.mandel_args(vp, row0=r0, rows=16)).result()
+            assert st == cg.OK
+            assert (img.cpu().numpy().reshape(16, 256) == whole[r0:r0 + 16]).all(), i
+            scratch.mul_(1.0001)  # eager work between replays
+            if i % 3 == 0:
+                torch.cuda.synchronize()
+        stats = s.stats()
+        assert stats["launches"] >= 24
+    finally:
+        s.shutdown()
