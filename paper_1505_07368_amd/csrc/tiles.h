@@ -37,43 +37,14 @@ __device__ inline uint32_t wave_id() { return threadIdx.x >> 6; }
 // empty -- the early exit is wave-uniform and no lane's count moves past
 // its escape.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ uint32_t escape_count(T cr, T ci, uint32_t max_iter, bool valid) {
-  // live: lanes still iterating, as a wave-wide ballot mask held in scalar
-  // registers.  Lanes that escaped keep computing (their values no longer
-  // matter), so the common path is the nine operations of one iteration
-  // plus scalar bookkeeping; a lane's count is frozen at its first escape,
-  // and the wave exits as soon as the ballot of live lanes is empty.
-  uint64_t live = __builtin_amdgcn_ballot_w64(valid);
-  uint32_t n = max_iter;
-  T zr = T(0), zi = T(0);
-  uint32_t it = 0;
-  if (max_iter == 0 || live == 0) return n;
-  do {
-    T zr2 = zr * zr;
-    T zi2 = zi * zi;
-    T mag = zr2 + zi2;
-    const bool esc = mag > T(4);
-    const uint64_t e = __builtin_amdgcn_ballot_w64(esc) & live;
-    if (__builtin_expect(e != 0, 0)) {
-      asm volatile("" ::: "memory");  // keep this rare path a branch, not selects
-      if (esc && n == max_iter) n = it;
-      live &= ~e;
-    }
-    T t = zr * zi;
-    T tt = t + t;
-    zi = tt + ci;
-    T d = zr2 - zi2;
-    zr = d + cr;
-    ++it;
-  } while (it < max_iter && live != 0);
-  return n;
-}
-
-// Two independent pixels per lane, interleaved, so each wave carries two
-// dependency chains (float only: it raises the issue rate of the fp32 loop;
-// the fp64 loop gains nothing from it).  The counts are those of
-// escape_count for each pixel.
+// Escape counts of two pixels per lane, interleaved, so each wave carries
+// two dependency chains (in float and in double) and the vector units stay
+// fed at five waves per SIMD.  The lanes still iterating are wave-wide
+// ballot masks held in scalar registers.  Lanes that escaped keep computing
+// (their values no longer matter), so the common path is the arithmetic of
+// one iteration per pixel plus scalar bookkeeping; a pixel's count is frozen
+// at its first escape (a rare branch), and the wave leaves as soon as both
+// masks are empty.  valid = false marks a lane's pixel as outside the tile.
 template <typename T>
 __device__ __forceinline__ void escape_count2(T cr0, T ci0, T cr1, T ci1, uint32_t max_iter,
                                               bool v0, bool v1, uint32_t& n0, uint32_t& n1) {
@@ -171,12 +142,7 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
       ci[k] = im_min + ym;
     }
     uint32_t n[2];
-    if constexpr (sizeof(T) == 4) {
-      escape_count2<T>(cr[0], ci[0], cr[1], ci[1], max_iter, v[0], v[1], n[0], n[1]);
-    } else {
-      n[0] = escape_count<T>(cr[0], ci[0], max_iter, v[0]);
-      n[1] = escape_count<T>(cr[1], ci[1], max_iter, v[1]);
-    }
+    escape_count2<T>(cr[0], ci[0], cr[1], ci[1], max_iter, v[0], v[1], n[0], n[1]);
 #pragma unroll
     for (int k = 0; k < 2; ++k)
       if (v[k]) out[(uint64_t)y[k] * width + x[k]] = (uint16_t)n[k];
