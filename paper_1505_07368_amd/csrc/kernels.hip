@@ -357,7 +357,7 @@ __device__ __forceinline__ void run_inline_stages(KArgsC& a, uint32_t slot, uint
 
 // LDS of the full variant: the largest work tile, two buffers of a bf16 GEMM
 // slice at TE = 128.  The light variant only needs the drain scratch.
-constexpr uint32_t kSmemBytes = 2 * (2 * 128 * 40 * 2);
+constexpr uint32_t kSmemBytes = 2 * (2 * 128 * (kBf16SliceK + 8) * 2);
 
 // ---- one launch per message -------------------------------------------------
 
@@ -809,7 +809,12 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) drain_kernel_full(KArgs) { drain_body<true>(kargs()); }
+// The full variant asks for two waves per SIMD (at most 256 registers,
+// accumulation registers included): two workgroups per compute unit.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+drain_kernel_full(KArgs) {
+  drain_body<true>(kargs());
+}
 
 // The light variant asks for five waves per SIMD (at most 96 registers).
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))

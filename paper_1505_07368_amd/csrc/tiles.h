@@ -233,7 +233,7 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const uint32_t idx = t + kThreads * q;
-        const uint32_t row = idx >> 2, kq = (idx & 3) * 4;
+        const uint32_t row = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
         const uint32_t gr = tm * TE + row, gk = k0 + kq;
         ra[q] = (gr < n && gk < n) ? *reinterpret_cast<const float4*>(A + (uint64_t)gr * n + gk)
                                    : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -249,7 +249,7 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const uint32_t idx = t + kThreads * q;
-        const uint32_t row = idx >> 2, kq = (idx & 3) * 4;
+        const uint32_t row = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
         As[(kq + 0) * TE + row] = ra[q].x;
         As[(kq + 1) * TE + row] = ra[q].y;
         As[(kq + 2) * TE + row] = ra[q].z;
@@ -297,17 +297,22 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
                   acc[i][j]);
 }
 
-// bfloat16 inputs: v_mfma_f32_32x32x16_bf16, k slices of 32.  Both operands
+// bfloat16 inputs: v_mfma_f32_32x32x16_bf16, k slices of kBf16SliceK.  Both operands
 // are kept k-contiguous in LDS ([row][k] for A, [column][k] for B, rows
 // padded to 80 bytes) so each lane reads its 8 k values with one 16-byte
 // LDS load.  B is transposed on the way in: a thread loads an 8 (k) x 8 (n)
 // block as eight 16-byte rows and regroups it in registers with byte
-// permutes into eight 16-byte columns.  smem: 2 x 2 x TE x 40 bf16.
+// permutes into eight 16-byte columns.  smem: 2 x 2 x TE x (kBf16SliceK + 8)
+// bf16.
+// k per LDS slice of the bf16 tile: long enough that a slice's matrix-core
+// work covers the next slice's global loads.
+constexpr int kBf16SliceK = 64;
+
 template <int TE>
 __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
                                float* __restrict__ C, uint32_t n, uint32_t tile,
                                uint16_t* smem) {
-  constexpr int BK = 32;
+  constexpr int BK = kBf16SliceK;
   constexpr int LD = BK + 8;
   constexpr int WB = TE / 64;
   constexpr int QA = TE * BK / 8 / kThreads;  // 16-byte A chunks per thread
@@ -360,7 +365,7 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
 #pragma unroll
       for (int q = 0; q < QA; ++q) {
         const uint32_t idx = t + kThreads * q;
-        const uint32_t row = idx >> 2, kc = (idx & 3) * 8;
+        const uint32_t row = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
         const uint32_t gr = tm * TE + row, gk = k0 + kc;
         ra[q] = (gr < n && gk < n) ? *reinterpret_cast<const uint4*>(A + (uint64_t)gr * n + gk)
                                    : make_uint4(0, 0, 0, 0);
@@ -382,7 +387,7 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
 #pragma unroll
       for (int q = 0; q < QA; ++q) {
         const uint32_t idx = t + kThreads * q;
-        const uint32_t row = idx >> 2, kc = (idx & 3) * 8;
+        const uint32_t row = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
         *reinterpret_cast<uint4*>(As + row * LD + kc) = ra[q];
       }
       if (t < (uint32_t)NBB) {
