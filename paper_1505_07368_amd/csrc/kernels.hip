@@ -789,8 +789,9 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
       s_exit = ex;
       if (!ex) {
         // A few sentinel workgroups poll with a short back-off (reply
-        // latency); the rest back off further while idle.
-        const uint32_t cap = blockIdx.x < kSentinels ? 1u : 8u;
+        // latency), and so does a workgroup holding a reserved index (the
+        // next published tile is its to run); the rest back off further.
+        const uint32_t cap = (blockIdx.x < kSentinels || holding) ? 1u : 8u;
         idle_rounds = idle_rounds < cap ? idle_rounds + 1 : cap;
         backoff_sleep(idle_rounds);
       }
