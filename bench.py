@@ -393,6 +393,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline leg only")
+    ap.add_argument("--legs", default="fp64,forms,small,gemm,pipeline,serving",
+                    help="comma list of the legs to run beside the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
     ap.add_argument("--mandel-tile-px", type=int, default=0,
@@ -457,7 +459,8 @@ def main():
             "kernel": "drain_kernel_light", "launches": head["kernel_launches"],
             "avg_launch_ms": round(per_launch_ms, 4),
             "ops_per_launch": head["iters_per_step"] * OPS_PER_ITER}
-    if not args.quick:
+    legs = set() if args.quick else set(args.legs.split(","))
+    if "fp64" in legs:
         log("[bench] batched fp64")
         f64 = mandel_leg(cg, torch, "batched", cg.F64, max(2, args.steps // 2), 1, seeds, True,
                          tune=tuned.get("mandel"))
@@ -467,11 +470,13 @@ def main():
             result["fp64"]["alu_frac"] = round(
                 f64["iters_per_step"] * max(2, args.steps // 2) * OPS_PER_ITER
                 / (f64["kernel_ms_total"] * 1e-3) / VALU_LANE_OPS, 4)
+    if "forms" in legs:
         for mode in ("persistent", "plain", "plain_graph"):
             log(f"[bench] {mode} fp32")
             r = mandel_leg(cg, torch, mode, cg.F32, max(2, args.steps // 2), 1, seeds,
                            tune=tuned.get("mandel") if mode != "plain" else None)
             result[mode] = {k: r[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
+    if "small" in legs:
         small = {}
         for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096)):
             for window in ((1, 64, 1024) if kind == "echo" else (256,)):
@@ -485,6 +490,7 @@ def main():
                     row["batched"]["msgs_per_s"] / row["plain"]["msgs_per_s"], 2)
                 small[f"{kind}_w{window}"] = row
         result["small_messages"] = small
+    if "gemm" in legs:
         for dt in ("f32", "bf16"):
             tc = (0, 0, 0, 0)
             if not args.no_tune:
@@ -493,12 +499,17 @@ def main():
                 tuned[f"gemm_{dt}_tile_class"] = tc
             log(f"[bench] gemm batch {dt}")
             result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt, tile_class=tc)
+    if "pipeline" in legs:
         log("[bench] pipeline")
         result["pipeline"] = pipeline_leg(cg, torch)
+    if "serving" in legs:
         serving = {}
         for rate in (1e4, 1e5, 1e6):
-            log(f"[bench] serving {rate:g}/s")
-            serving[f"{rate:g}"] = serving_leg(cg, torch, rate)
+            # at most 2e5 arrivals per rate: above capacity the backlog, not
+            # the arrival window, sets the run time
+            dur = min(2.0, 2e5 / rate)
+            log(f"[bench] serving {rate:g}/s for {dur:g} s")
+            serving[f"{rate:g}"] = serving_leg(cg, torch, rate, duration_s=dur)
         result["serving"] = serving
     result["tuned"] = tuned
     if not args.no_cpu:
