@@ -7,7 +7,8 @@
       --copy-kernel neg_kernel --copy-bytes 1073741824 --command "..." ...
 
 prints a markdown summary: per-dispatch durations of the kernel from a
---kernel-trace run, and its HBM traffic per dispatch from two --pmc runs
+--kernel-trace run, optionally matrix-core utilisation from a --pmc run
+(--mfma), and its HBM traffic per dispatch from two --pmc runs
 (FETCH_SIZE, WRITE_SIZE, in KiB per dispatch).  Each counter is scaled by what
 it reads for a copy kernel of known size (bytes read = bytes written =
 --copy-bytes per dispatch), since the counters need not count every byte
@@ -55,15 +56,37 @@ def counter_kib(pmc_csv: str, kernel: str, counter: str) -> list[float]:
     return [float(r["Counter_Value"]) for r in rows]
 
 
+def mfma_dispatches(pmc_csv: str, kernel: str, n_xcc: int, simds: int) -> list[dict]:
+    """Per dispatch of `kernel`: matrix-core utilisation and flops from
+    SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE and SQ_INSTS_VALU_MFMA_MOPS_*
+    (512 flops per MOP).  GRBM_GUI_ACTIVE is reported summed over the
+    chip's XCCs, so the active cycles of one XCC are that sum / n_xcc."""
+    by = {}
+    for r in _rows(pmc_csv):
+        if kernel in r["Kernel_Name"]:
+            by.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = []
+    for did in sorted(by):
+        c = by[did]
+        active = c.get("GRBM_GUI_ACTIVE", 0.0) / n_xcc
+        busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        mops = sum(v for k, v in c.items() if k.startswith("SQ_INSTS_VALU_MFMA_MOPS_"))
+        out.append({"dispatch": did, "util": busy / (active * simds) if active else float("nan"),
+                     "flops": mops * 512.0, "active_cycles": active})
+    return out
+
+
 def read_summary(path: str) -> dict:
     """The `key: value` lines of a summary written by this module."""
     out = {}
     if not os.path.exists(path):
         return out
+    seen = False
     with open(path) as f:
         for line in f:
             line = line.strip()
-            if line.startswith("- ") and ": " in line:
+            seen = seen or line == "Machine-readable:"
+            if seen and line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 out[k.strip()] = v.strip()
     return out
@@ -86,6 +109,11 @@ def main(argv=None):
     ap.add_argument("--copy-kernel", default="neg_kernel")
     ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     ap.add_argument("--pmc-last", type=int, default=0)
+    ap.add_argument("--mfma", help="--pmc csv with SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE, "
+                    "SQ_INSTS_VALU_MFMA_MOPS_*")
+    ap.add_argument("--xcc", type=int, default=8)
+    ap.add_argument("--simds", type=int, default=1024)
+    ap.add_argument("--note", action="append", default=[])
     ap.add_argument("--command", action="append", default=[])
     a = ap.parse_args(argv)
 
@@ -94,8 +122,8 @@ def main(argv=None):
     lines = [f"# {a.title or a.kernel}", "", "Commands (run from the repository root on the GPU; "
              "`cd /tmp && export TMPDIR=/tmp` first):", ""]
     lines += [f"    {c}" for c in a.command]
-    lines += ["", f"Kernel `{a.kernel}`: {len(dur)} dispatches in the trace; "
-              f"the last {len(sel)} are the timed steps.", ""]
+    which = f"the last {len(sel)} are the timed steps" if a.last else "all are summarised"
+    lines += ["", f"Kernel `{a.kernel}`: {len(dur)} dispatches in the trace; {which}.", ""]
     lines += ["| dispatches | mean ms | min ms | max ms |", "|---|---|---|---|",
               f"| {len(sel)} | {_mean(sel) / 1e6:.4f} | {min(sel) / 1e6:.4f} | "
               f"{max(sel) / 1e6:.4f} |", ""]
@@ -121,6 +149,15 @@ def main(argv=None):
                    "fetch_bytes_per_dispatch": f"{fb:.0f}",
                    "write_bytes_per_dispatch": f"{wb:.0f}",
                    "traffic_bytes_per_dispatch": f"{fb + wb:.0f}"})
+    if a.mfma:
+        md = mfma_dispatches(a.mfma, a.kernel, a.xcc, a.simds)
+        lines += [f"Matrix cores per dispatch (busy cycles / (active cycles of one XCC x "
+                  f"{a.simds} SIMDs); flops = MFMA MOPs x 512):", "",
+                  "| dispatch | MFMA utilisation | GFLOP |", "|---|---|---|"]
+        lines += [f"| {d['dispatch']} | {100 * d['util']:.1f}% | {d['flops'] / 1e9:.2f} |"
+                  for d in md]
+        lines += [""]
+    lines += [f"- {n}" for n in a.note] + ([""] if a.note else [])
     lines += ["Machine-readable:", ""] + [f"- {k}: {v}" for k, v in kv.items()]
     print("\n".join(lines))
 
