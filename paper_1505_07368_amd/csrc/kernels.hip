@@ -362,7 +362,8 @@ constexpr uint32_t kSmemBytes = 2 * (2 * 128 * (kBf16SliceK + 8) * 2);
 // ---- one launch per message -------------------------------------------------
 
 template <bool kFull>
-__global__ void __launch_bounds__(kThreads) plain_kernel(KArgs, Desc d, uint32_t ntiles) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+plain_kernel(KArgs, Desc d, uint32_t ntiles) {
   KArgsC& a = kargs();
   __shared__ __align__(16) uint8_t smem[kSmemBytes];
   __shared__ uint32_t s_dec;

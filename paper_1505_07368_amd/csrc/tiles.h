@@ -19,6 +19,25 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
+
+// Global-memory (address space 1) views of the pointers a message carries.
+// Accesses through them are global_* instructions, counted by the vector
+// memory counter only; through generic pointers they would be flat_*
+// instructions, which also count against the LDS counter, so every wait for
+// an LDS read would also wait for the outstanding global prefetch.
+#define CAF_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ CAF_GLOBAL T* global_ptr(T* p) {
+  return (CAF_GLOBAL T*)p;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// A 16-byte global load, returned as V (float4 or uint4).
+template <typename V, typename T>
+__device__ __forceinline__ V load_global(const CAF_GLOBAL T* p) {
+  static_assert(sizeof(V) == 16, "16-byte loads");
+  const u32x4 r = *reinterpret_cast<const CAF_GLOBAL u32x4*>(p);
+  return __builtin_bit_cast(V, r);
+}
 __device__ inline uint32_t wave_id() { return threadIdx.x >> 6; }
 
 // ---------------------------------------------------------------------------
@@ -172,7 +191,7 @@ __device__ __forceinline__ void tile_coords(uint32_t tile, uint32_t n, uint32_t 
 }
 
 template <int TE>
-__device__ __forceinline__ void store_c(float* C, uint32_t n, uint32_t row_base,
+__device__ __forceinline__ void store_c(CAF_GLOBAL float* C, uint32_t n, uint32_t row_base,
                                         uint32_t col_base, const floatx16& acc) {
   const uint32_t lane = lane_id();
   const uint32_t col = col_base + (lane & 31);
@@ -198,6 +217,9 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
   constexpr int SLICE = 2 * BK * TE;        // floats per LDS buffer
   uint32_t tm, tn;
   tile_coords(tile, n, TE, tm, tn);
+  const auto Ag = global_ptr(A);
+  const auto Bg = global_ptr(B);
+  const auto Cg = global_ptr(C);
   const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
   const uint32_t wm = w >> 1, wn = w & 1;
   const bool vec = (n % 4u) == 0 && ((reinterpret_cast<uintptr_t>(A) |
@@ -235,11 +257,11 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
         const uint32_t idx = t + kThreads * q;
         const uint32_t row = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
         const uint32_t gr = tm * TE + row, gk = k0 + kq;
-        ra[q] = (gr < n && gk < n) ? *reinterpret_cast<const float4*>(A + (uint64_t)gr * n + gk)
+        ra[q] = (gr < n && gk < n) ? load_global<float4>(Ag + (uint64_t)gr * n + gk)
                                    : make_float4(0.f, 0.f, 0.f, 0.f);
         const uint32_t kr = idx / (TE / 4), c = (idx % (TE / 4)) * 4;
         const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        rb[q] = (gk2 < n && gc < n) ? *reinterpret_cast<const float4*>(B + (uint64_t)gk2 * n + gc)
+        rb[q] = (gk2 < n && gc < n) ? load_global<float4>(Bg + (uint64_t)gk2 * n + gc)
                                     : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     };
@@ -279,10 +301,10 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
       for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
         const uint32_t row = idx / BK, kk = idx % BK;
         const uint32_t gr = tm * TE + row, gk = k0 + kk;
-        As[kk * TE + row] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : 0.f;
+        As[kk * TE + row] = (gr < n && gk < n) ? Ag[(uint64_t)gr * n + gk] : 0.f;
         const uint32_t kr = idx / TE, c = idx % TE;
         const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        Bs[kr * TE + c] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : 0.f;
+        Bs[kr * TE + c] = (gk2 < n && gc < n) ? Bg[(uint64_t)gk2 * n + gc] : 0.f;
       }
       __syncthreads();
       mfma_slice(As, Bs);
@@ -293,16 +315,16 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
   for (int i = 0; i < WB; ++i)
 #pragma unroll
     for (int j = 0; j < WB; ++j)
-      store_c<TE>(C, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
+      store_c<TE>(Cg, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
                   acc[i][j]);
 }
 
 // bfloat16 inputs: v_mfma_f32_32x32x16_bf16, k slices of kBf16SliceK.  Both operands
 // are kept k-contiguous in LDS ([row][k] for A, [column][k] for B, rows
-// padded to 80 bytes) so each lane reads its 8 k values with one 16-byte
-// LDS load.  B is transposed on the way in: a thread loads an 8 (k) x 8 (n)
-// block as eight 16-byte rows and regroups it in registers with byte
-// permutes into eight 16-byte columns.  smem: 2 x 2 x TE x (kBf16SliceK + 8)
+// padded by 16 bytes) so each lane reads its 8 k values with one 16-byte
+// LDS load.  B is transposed on the way in: a thread loads a 4 (k) x 8 (n)
+// block as four 16-byte rows and regroups it in registers with byte
+// permutes into eight 8-byte columns.  smem: 2 x 2 x TE x (kBf16SliceK + 8)
 // bf16.
 // k per LDS slice of the bf16 tile: long enough that a slice's matrix-core
 // work covers the next slice's global loads.
@@ -320,6 +342,9 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
   constexpr int SLICE = 2 * TE * LD;          // bf16 per LDS buffer
   uint32_t tm, tn;
   tile_coords(tile, n, TE, tm, tn);
+  const auto Ag = global_ptr(A);
+  const auto Bg = global_ptr(B);
+  const auto Cg = global_ptr(C);
   const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
   const uint32_t wm = w >> 1, wn = w & 1;
   const bool vec = (n % 8u) == 0 && ((reinterpret_cast<uintptr_t>(A) |
@@ -356,28 +381,48 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
   };
 
   if (vec) {
-    uint4 ra[QA];
-    uint4 rb[8];  // one 8x8 block of B (threads t < NBB)
-    // k-block index fastest: neighbouring lanes write different 16-byte
-    // chunks of one LDS row pair instead of rows 8 apart (same banks)
-    const uint32_t kb = t % (BK / 8), nb = t / (BK / 8);
-    auto gload = [&](uint32_t k0) {
+    // Per-thread sources, computed once per tile.  Rows of A and columns of
+    // B outside the matrix are clamped to valid ones instead of zeroed: they
+    // only feed rows / columns of C that are not stored.  k runs past n only
+    // in a partial last slice, which takes the checked loads (zeros).
+    constexpr int NB4 = (BK / 4) * (TE / 8);  // 4 (k) x 8 (n) blocks of B per slice
+    static_assert(NB4 <= kThreads, "one B block per thread at most");
+    const uint32_t kb = t % (BK / 4), nb = t / (BK / 4);  // k-block fastest
+    const CAF_GLOBAL uint16_t* pa[QA];
+    uint32_t kca[QA];
 #pragma unroll
-      for (int q = 0; q < QA; ++q) {
-        const uint32_t idx = t + kThreads * q;
-        const uint32_t row = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
-        const uint32_t gr = tm * TE + row, gk = k0 + kc;
-        ra[q] = (gr < n && gk < n) ? *reinterpret_cast<const uint4*>(A + (uint64_t)gr * n + gk)
-                                   : make_uint4(0, 0, 0, 0);
-      }
-      if (t < (uint32_t)NBB) {
-        const uint32_t gc = tn * TE + nb * 8;
+    for (int q = 0; q < QA; ++q) {
+      const uint32_t idx = t + kThreads * q;
+      const uint32_t row = idx / (BK / 8);
+      kca[q] = (idx % (BK / 8)) * 8;
+      const uint32_t gr = min(tm * TE + row, n - 1u);
+      pa[q] = Ag + (uint64_t)gr * n + kca[q];
+    }
+    uint32_t gcol = tn * TE + nb * 8;
+    if (gcol >= n) gcol = 0;
+    const CAF_GLOBAL uint16_t* pb = Bg + (uint64_t)(kb * 4) * n + gcol;
+    const bool has_b = t < (uint32_t)NB4;
+    uint4 ra[QA], rb[4];
+    auto gload = [&](uint32_t k0, bool checked) {
+      if (!checked) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const uint32_t gk = k0 + kb * 8 + r;
-          rb[r] = (gk < n && gc < n)
-                      ? *reinterpret_cast<const uint4*>(B + (uint64_t)gk * n + gc)
-                      : make_uint4(0, 0, 0, 0);
+        for (int q = 0; q < QA; ++q) ra[q] = load_global<uint4>(pa[q] + k0);
+        if (has_b) {
+          const CAF_GLOBAL uint16_t* p = pb + (uint64_t)k0 * n;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) rb[r] = load_global<uint4>(p + (uint64_t)r * n);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < QA; ++q)
+          ra[q] = (k0 + kca[q] < n) ? load_global<uint4>(pa[q] + k0) : make_uint4(0, 0, 0, 0);
+        if (has_b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t gk = k0 + kb * 4 + r;
+            rb[r] = gk < n ? load_global<uint4>(pb + (uint64_t)(k0 + r) * n)
+                           : make_uint4(0, 0, 0, 0);
+          }
         }
       }
     };
@@ -387,34 +432,34 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
 #pragma unroll
       for (int q = 0; q < QA; ++q) {
         const uint32_t idx = t + kThreads * q;
-        const uint32_t row = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
-        *reinterpret_cast<uint4*>(As + row * LD + kc) = ra[q];
+        *reinterpret_cast<uint4*>(As + (idx / (BK / 8)) * LD + kca[q]) = ra[q];
       }
-      if (t < (uint32_t)NBB) {
+      if (has_b) {
         // column c of the block: k pairs (2m, 2m+1) from rows 2m and 2m+1,
         // low halves for even c, high halves for odd c
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-          uint32_t col[4];
+          uint32_t col[2];
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
+          for (int m = 0; m < 2; ++m) {
             const uint4 lo = rb[2 * m], hi = rb[2 * m + 1];
             const uint32_t wl = (c >> 1) == 0 ? lo.x : (c >> 1) == 1 ? lo.y : (c >> 1) == 2 ? lo.z : lo.w;
             const uint32_t wh = (c >> 1) == 0 ? hi.x : (c >> 1) == 1 ? hi.y : (c >> 1) == 2 ? hi.z : hi.w;
             col[m] = __builtin_amdgcn_perm(wh, wl, (c & 1) ? 0x07060302u : 0x05040100u);
           }
-          *reinterpret_cast<uint4*>(Bs + (nb * 8 + c) * LD + kb * 8) =
-              make_uint4(col[0], col[1], col[2], col[3]);
+          *reinterpret_cast<uint2*>(Bs + (nb * 8 + c) * LD + kb * 4) = make_uint2(col[0], col[1]);
         }
       }
     };
-    gload(0);
+    const uint32_t nk = (n + BK - 1) / BK;
+    const uint32_t last_checked = (n % BK) ? nk - 1 : nk;  // index of the partial slice, if any
+    gload(0, last_checked == 0);
     lstore(smem);
     __syncthreads();
     uint32_t cur = 0;
-    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
-      const bool more = k0 + BK < n;
-      if (more) gload(k0 + BK);
+    for (uint32_t k = 0; k < nk; ++k) {
+      const bool more = k + 1 < nk;
+      if (more) gload((k + 1) * BK, k + 1 == last_checked);
       const uint16_t* buf = smem + cur * SLICE;
       mfma_slice(buf, buf + TE * LD);
       if (more) lstore(smem + (cur ^ 1u) * SLICE);
@@ -428,10 +473,10 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
       for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
         const uint32_t row = idx / BK, kk = idx % BK;
         const uint32_t gr = tm * TE + row, gk = k0 + kk;
-        As[row * LD + kk] = (gr < n && gk < n) ? A[(uint64_t)gr * n + gk] : (uint16_t)0;
+        As[row * LD + kk] = (gr < n && gk < n) ? Ag[(uint64_t)gr * n + gk] : (uint16_t)0;
         const uint32_t kr = idx / TE, c = idx % TE;
         const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        Bs[c * LD + kr] = (gk2 < n && gc < n) ? B[(uint64_t)gk2 * n + gc] : (uint16_t)0;
+        Bs[c * LD + kr] = (gk2 < n && gc < n) ? Bg[(uint64_t)gk2 * n + gc] : (uint16_t)0;
       }
       __syncthreads();
       mfma_slice(As, Bs);
@@ -442,7 +487,7 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
   for (int i = 0; i < WB; ++i)
 #pragma unroll
     for (int j = 0; j < WB; ++j)
-      store_c<TE>(C, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
+      store_c<TE>(Cg, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
                   acc[i][j]);
 }
 
