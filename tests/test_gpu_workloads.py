@@ -10,7 +10,9 @@ oracle one by one, plus properties that hold for every output:
   * the grouped GEMM batch: n drawn from {64, 128, 256, 512}, fp32 and bf16,
     both output-tile edges;
   * the serving mix: Mandelbrot squares 64^2..512^2 at max_iter 256..4096 and
-    fp32 GEMMs n = 32..512 through the non-blocking persistent system.
+    fp32 GEMMs n = 32..512 through the non-blocking persistent system;
+  * the GEMM leg's 4096-request batch and the pipeline leg's 100,000 chains
+    as the benchmark runs them.
 """
 import numpy as np
 import pytest
@@ -182,3 +184,119 @@ def test_serving_mix_sampled():
             n = A.shape[0]
             err = rel_fro(out.cpu().numpy().reshape(n, n), oracle.gemm(A, B))
             assert err <= 1e-5, (n, err)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gemm_bench_batch_full_size(dtype):
+    """The benchmark's GEMM leg as timed: 4096 requests, n ~ U{64..512},
+    inputs drawn on the device, batched drain with max_batch 1024.  Every
+    output is checked finite; one message of each size against the oracle
+    (inputs copied back)."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    count = 4096
+    sizes = gen.gemm_sizes(0, count).astype(np.int64)
+    nn = sizes * sizes
+    offs = np.concatenate([[0], np.cumsum(nn)[:-1]])
+    total = int(nn.sum())
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    A = torch.rand(total, generator=g, device="cuda") * 2 - 1
+    B = torch.rand(total, generator=g, device="cuda") * 2 - 1
+    code = cg.F32
+    if dtype == "bf16":
+        A, B, code = A.to(torch.bfloat16), B.to(torch.bfloat16), cg.BF16
+    C = torch.full((total,), float("nan"), device="cuda")
+    esz = A.element_size()
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=count, max_batch=1024)
+    try:
+        a = s.spawn(cg.BHV_GEMM)
+        args = np.zeros(count, cg.NP_GEMM)
+        args["n"] = sizes
+        args["in_dtype"] = code
+        bufs = np.zeros(2 * count, cg.NP_BUF)
+        bufs["data"][0::2] = A.data_ptr() + offs.astype(np.uint64) * esz
+        bufs["data"][1::2] = B.data_ptr() + offs.astype(np.uint64) * esz
+        bufs["numel"][0::2] = nn
+        bufs["numel"][1::2] = nn
+        bufs["dtype"] = code
+        bufs["on_device"] = 1
+        idx = np.arange(count, dtype=np.uint64)
+        msgs = np.zeros(count, cg.NP_MSG)
+        msgs["actor"] = a
+        msgs["n_in"] = 2
+        msgs["args"] = args.ctypes.data + idx * args.itemsize
+        msgs["args_bytes"] = args.itemsize
+        msgs["in_"] = bufs.ctypes.data + idx * 2 * bufs.itemsize
+        msgs["out"]["data"] = C.data_ptr() + offs.astype(np.uint64) * 4
+        msgs["out"]["numel"] = nn
+        msgs["out"]["dtype"] = cg.F32
+        msgs["out"]["on_device"] = 1
+        torch.cuda.synchronize()
+        rc, _, st, _ = cg.drive_array(s, msgs, (args, bufs, A, B, C), window=count)
+        assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+    finally:
+        s.shutdown()
+    assert torch.isfinite(C).all()
+    for size in (64, 128, 256, 512):
+        i = int(np.nonzero(sizes == size)[0][0])
+        o, m = int(offs[i]), size * size
+        if dtype == "bf16":
+            Ah = A[o:o + m].view(torch.int16).cpu().numpy().view(np.uint16).reshape(size, size)
+            Bh = B[o:o + m].view(torch.int16).cpu().numpy().view(np.uint16).reshape(size, size)
+        else:
+            Ah = A[o:o + m].cpu().numpy().reshape(size, size)
+            Bh = B[o:o + m].cpu().numpy().reshape(size, size)
+        err = rel_fro(C[o:o + m].cpu().numpy().reshape(size, size), oracle.gemm(Ah, Bh, dtype))
+        assert err <= 1e-5, (size, err)
+
+
+def test_pipeline_bench_size_sampled():
+    """The benchmark's pipeline leg at full size: 100,000 GEMM(128) -> tanh ->
+    row-sum chains with device forwarding (persistent drain); every reply
+    finite, sampled chains against the oracle chain."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    n, chains = 128, 100000
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    A = torch.rand(chains * n * n, generator=g, device="cuda") * 2 - 1
+    B = torch.rand(chains * n * n, generator=g, device="cuda") * 2 - 1
+    Y = torch.full((chains * n,), float("nan"), device="cuda")
+    s = cg.System(mode="persistent", arena_bytes=4 << 30, ring_slots=4096)
+    try:
+        rs = s.spawn(cg.BHV_ROWSUM, n=n)
+        th = s.spawn(cg.BHV_TANH, n=n, forward_to=rs)
+        gm = s.spawn(cg.BHV_GEMM, n=n)
+        args = np.zeros(1, cg.NP_GEMM)
+        args["n"] = n
+        args["in_dtype"] = cg.F32
+        idx = np.arange(chains, dtype=np.uint64)
+        bufs = np.zeros(chains * 2, cg.NP_BUF)
+        bufs["data"][0::2] = A.data_ptr() + idx * (n * n * 4)
+        bufs["data"][1::2] = B.data_ptr() + idx * (n * n * 4)
+        bufs["numel"] = n * n
+        bufs["dtype"] = cg.F32
+        bufs["on_device"] = 1
+        msgs = np.zeros(chains, cg.NP_MSG)
+        msgs["actor"] = gm
+        msgs["n_in"] = 2
+        msgs["args"] = args.ctypes.data
+        msgs["args_bytes"] = args.itemsize
+        msgs["in_"] = bufs.ctypes.data + idx * 2 * bufs.itemsize
+        msgs["forward_to"] = th
+        msgs["out"]["data"] = Y.data_ptr() + idx * (n * 4)
+        msgs["out"]["numel"] = n
+        msgs["out"]["dtype"] = cg.F32
+        msgs["out"]["on_device"] = 1
+        torch.cuda.synchronize()
+        rc, _, st, _ = cg.drive_array(s, msgs, (args, bufs), window=1024)
+        assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+    finally:
+        s.shutdown()
+    assert torch.isfinite(Y).all()
+    for c in (0, 1, 4321, 77777, chains - 1):
+        a = A[c * n * n:(c + 1) * n * n].cpu().numpy().reshape(n, n)
+        b = B[c * n * n:(c + 1) * n * n].cpu().numpy().reshape(n, n)
+        err = rel_fro(Y[c * n:(c + 1) * n].cpu().numpy(), oracle.chain(a, b))
+        assert err <= 1e-5, (c, err)
