@@ -7,7 +7,7 @@ by the device name and a workload signature, so a later run can reuse them
 without re-timing.
 
 Tuned knobs:
-  * Mandelbrot: pixels per work tile (1024, 2048, 4096) and the drain grid
+  * Mandelbrot: pixels per work tile (512, 1024, 2048, 4096) and the drain grid
     (all workgroups resident, or half of them);
   * GEMM: output-tile edge (64 or 128) per size class (n <= 64, <= 128,
     <= 256, > 256).
@@ -73,7 +73,7 @@ def mandel_messages(actor, viewports, tile_rows=64, fp=cg.F32):
 
 
 def tune_mandel(torch, viewports, mode="batched", cache_path=None, reps=2,
-                pxs=(1024, 2048, 4096), fp=cg.F32):
+                pxs=(512, 1024, 2048, 4096), fp=cg.F32):
     """Returns {"mandel_tile_px": px, "grid": g} for the image workload."""
     key = f"{_device_name(torch)}|mandel|{mode}|fp{fp}|{len(viewports)}x" \
           f"{viewports[0].width}x{viewports[0].height}|{viewports[0].max_iter}"
