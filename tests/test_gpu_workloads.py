@@ -56,8 +56,8 @@ def _check_images(imgs, fp):
             assert (host[y] == ref[0]).all(), (seed, y, int((host[y] != ref[0]).sum()))
 
 
-@pytest.mark.parametrize("px,half_grid", [(512, False), (1024, False), (2048, False), (4096, False),
-                                          (2048, True)])
+@pytest.mark.parametrize("px,half_grid", [(512, False), (1024, False), (2048, False),
+                                          (4096, False), (2048, True)])
 def test_headline_batch_tile_candidates(px, half_grid):
     """Every (work tile, grid) candidate the autotuner may pick, in float."""
     import torch
