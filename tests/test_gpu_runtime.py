@@ -278,3 +278,36 @@ def test_plain_graph_replays_match_oracle():
         assert stats["launches"] >= 24
     finally:
         s.shutdown()
+
+
+def test_degenerate_and_maximum_arguments(sysm):
+    """Boundaries of the signatures: empty or oversized requests are refused
+    with CAF_E_INVALID before anything reaches the device; the largest
+    max_iter and a 1-pixel / 1x1 request are served exactly."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    from paper_1505_07368_amd.gen import Viewport
+    g = sysm.spawn(cg.BHV_GEMM)
+    A = torch.zeros(4, dtype=torch.float32, device="cuda")
+    assert sysm.request_raw(g, cg.caf_gemm_args(0, cg.F32), [A[:0], A[:0]])[0] == cg.E_INVALID
+    assert sysm.request_raw(g, cg.caf_gemm_args(16385, cg.F32), [A, A])[0] == cg.E_INVALID
+    assert sysm.request_raw(g, cg.caf_gemm_args(2, cg.F64), [A, A])[0] == cg.E_INVALID
+    m = sysm.spawn(cg.BHV_MANDELBROT)
+    vp = gen.tiny_viewport()
+    assert sysm.request_raw(m, cg.mandel_args(vp, max_iter=65536))[0] == cg.E_INVALID
+    assert sysm.request_raw(m, cg.mandel_args(Viewport(0, 0, 1, 1, 0, 1, 10)))[0] == cg.E_INVALID
+    assert sysm.request_raw(m, cg.mandel_args(vp, fp=cg.I32))[0] == cg.E_INVALID
+    e = sysm.spawn(cg.BHV_NOOP)
+    assert sysm.request_raw(e, None, [np.zeros(0, np.int32)])[0] == cg.E_INVALID
+    # max_iter = 65535 at c = 0 (never escapes) and 1 at c = 3 (escapes at once)
+    for c, mi, expect in [(0j, 65535, 65535), (3 + 0j, 1, 1), (3 + 0j, 65535, 1)]:
+        st, img = sysm.request(m, cg.mandel_args(Viewport(c.real, c.imag, 0, 0, 1, 1, mi))).result()
+        assert st == cg.OK and int(img.cpu()[0]) == expect, (c, mi)
+    # 1x1 GEMM in both input types
+    for code, dt in ((cg.F32, torch.float32), (cg.BF16, torch.bfloat16)):
+        a1 = torch.full((1,), 3.0, dtype=dt, device="cuda")
+        b1 = torch.full((1,), -2.0, dtype=dt, device="cuda")
+        torch.cuda.synchronize()
+        st, c1 = sysm.request(g, cg.caf_gemm_args(1, code), inputs=[a1, b1]).result()
+        assert st == cg.OK and float(c1.cpu()[0]) == -6.0
+    assert sysm.drain(30) == cg.OK

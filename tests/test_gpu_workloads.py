@@ -300,3 +300,30 @@ def test_pipeline_bench_size_sampled():
         b = B[c * n * n:(c + 1) * n * n].cpu().numpy().reshape(n, n)
         err = rel_fro(Y[c * n:(c + 1) * n].cpu().numpy(), oracle.chain(a, b))
         assert err <= 1e-5, (c, err)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gemm_large_single_message(dtype):
+    """One n = 1024 request (64 tiles of 128, 16 k slices) through the
+    batched drain, against the FP64 oracle."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    n = 1024
+    A, B = gen.gemm_pair(4242, n, dtype)
+    if dtype == "f32":
+        At, Bt, code = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), cg.F32
+    else:
+        At = torch.from_numpy(A.view(np.int16)).cuda().view(torch.bfloat16)
+        Bt = torch.from_numpy(B.view(np.int16)).cuda().view(torch.bfloat16)
+        code = cg.BF16
+    s = cg.System(mode="batched", arena_bytes=64 << 20)
+    try:
+        g = s.spawn(cg.BHV_GEMM)
+        torch.cuda.synchronize()
+        st, C = s.request(g, cg.caf_gemm_args(n, code), inputs=[At, Bt]).result()
+        assert st == cg.OK
+        c = C.cpu().numpy().reshape(n, n)
+    finally:
+        s.shutdown()
+    err = rel_fro(c, oracle.gemm(A, B, dtype))
+    assert err <= 1e-5, err
