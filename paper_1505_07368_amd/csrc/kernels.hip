@@ -19,8 +19,9 @@
 //    workgroup ever waits for one that may not be resident.  The
 //    workgroup finishing a message's last tile either publishes its reply
 //    (a completion record in host memory, released at system scope) or
-//    forwards the reply to the next actor of a pipeline as a new message
-//    on the device (no host round trip).
+//    forwards the reply to the next actor of a pipeline on the device (no
+//    host round trip): a stage of at most kInlineStageTiles tiles runs in
+//    that workgroup at once, a larger one is published as new work tiles.
 //
 //    A launch retires as a whole once it has been idle for idle_ticks with
 //    an empty mailbox (batched mode: tens of microseconds, so one launch
