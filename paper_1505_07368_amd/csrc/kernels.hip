@@ -618,9 +618,13 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (t == 0) {
-    st_dev_rel(&a.dctl->tiles_pub, pub + total);
-    st_dev_rel(&a.dctl->drained, L.d + cnt);
-    st_sys_rel(&a.hctl->drained, L.d + cnt);
+    // The fence and barrier above release the slots and tile map written by
+    // every thread, so the tiles are published first, without another fence.
+    // The unlock releases the drained counts: the host copy must never move
+    // backwards, so it lands before the next holder can write its own.
+    st_dev(&a.dctl->tiles_pub, pub + total);
+    st_dev(&a.dctl->drained, L.d + cnt);
+    st_sys(&a.hctl->drained, L.d + cnt);
     unlock_drain(a);
   }
   return true;
@@ -654,16 +658,18 @@ struct Claim {
   uint64_t next = 0, end = 0;  // tiles [next, end) are this workgroup's
 };
 
-__device__ __forceinline__ void reserve(KArgsC& a, Claim& c) {
+// Returns the published count it read (0 if it reserved nothing).
+__device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c) {
   const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
   const uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
-  if (cur >= pub) return;
+  if (cur >= pub) return 0;
   // guided self-scheduling: large chunks while plenty is published
   const uint64_t avail = pub - cur, g2 = 2ull * a.grid;
   const uint64_t k = avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4 : avail >= 2 * g2 ? 2 : 1;
   c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   c.end = c.next + k;
+  return pub;
 }
 
 // Publishes filler tiles for every reserved but unpublished index (caller
@@ -693,9 +699,11 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
   for (;;) {
     if (t == 0) {
       uint32_t cmd = CMD_IDLE;
-      if (c.next == c.end) reserve(a, c);
+      uint64_t pub = 0;
+      if (c.next == c.end) pub = reserve(a, c);
       if (c.next < c.end) {
-        const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
+        // the count read while reserving usually covers the new indices
+        if (c.next >= pub) pub = ld_dev(&a.dctl->tiles_pub);
         if (c.next < pub) {
           const uint64_t n = (c.end < pub ? c.end : pub) - c.next;
           s_g = c.next;
@@ -740,7 +748,10 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         }
         const uint32_t ntiles = __builtin_amdgcn_readfirstlane(s_slot.ntiles);
         const uint32_t tile = (uint32_t)(g - s_slot.tile_base);
-        if (ld_dev(&a.sstate[d.slot].status) == CAF_OK) run_tile<kFull>(a, d, tile, smem, &s_ctr);
+        // A failed tile stops the message's other tiles; a one-tile message
+        // cannot have failed before its tile runs.
+        if (ntiles == 1 || ld_dev(&a.sstate[d.slot].status) == CAF_OK)
+          run_tile<kFull>(a, d, tile, smem, &s_ctr);
         __syncthreads();
         if (t == 0) s_cont = finish_tile(a, d, ntiles, true) ? 1u : 0u;
         __syncthreads();

@@ -13,8 +13,10 @@
 //
 // Concurrency: one mutex (`mu`) guards the actor table, the slot pool, the
 // arena and the ring writer; a request takes it once in the common case.
-// The poller resolves completions in batches, taking the mutex once per
-// batch.
+// The poller never takes it: finished slots and unreferenced futures go onto
+// two lock-free stacks, which the next holder of the mutex empties into the
+// slot pool, the future pool and the arena.  (A contended mutex hand-off
+// costs the poller a sleep and a wake-up per batch of completions.)
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
@@ -152,6 +154,7 @@ struct caf_future {
   uint8_t inline_data[kInlineBytes] = {};
   Block out;                  // arena reply buffer owned by this future
   std::atomic<int> refs{2};   // the caller's handle + the request in flight
+  caf_future* next_retired = nullptr;  // link on the retired-future stack
   int64_t t_issue = 0, t_done = 0;
   DriveQ* q = nullptr;        // driver notification (optional)
   uint32_t tag = 0;
@@ -163,6 +166,7 @@ struct SlotInfo {
   caf_future* fut = nullptr;
   Block temps[kMaxTemps];  // staged inputs, intermediate and unwanted replies
   uint32_t ntemps = 0;
+  uint32_t next_retired = 0;  // slot + 1 below this one on the retired-slot stack
 };
 
 // An instantiated graph of one message's plain launches (one kernel node per
@@ -207,6 +211,9 @@ struct caf_gpu_system {
   bool shut = false;
   std::atomic<uint64_t> outstanding{0};
   std::atomic<uint32_t> waiters{0};
+  // Returned without mu: pushed by any thread, emptied whole under mu.
+  std::atomic<uint32_t> retired_slots{0};  // slot + 1 of the top entry, 0 if empty
+  std::atomic<caf_future*> retired_futs{nullptr};
   // drain kernel
   std::mutex launch_mu;
   std::atomic<uint32_t> launched_gen{0};
@@ -252,6 +259,16 @@ caf_future* new_future(caf_gpu_system* s) {  // mu held
   return f;
 }
 
+// Pushes a finished slot (poller thread; its SlotInfo is no longer read by
+// anyone else until reclaim() returns it to the pool).
+void retire_slot(caf_gpu_system* s, uint32_t slot) {
+  uint32_t top = s->retired_slots.load(std::memory_order_relaxed);
+  do {
+    s->slots[slot].next_retired = top;
+  } while (!s->retired_slots.compare_exchange_weak(top, slot + 1, std::memory_order_release,
+                                                   std::memory_order_relaxed));
+}
+
 void put_ref(caf_future* f) {  // mu not held
   if (f->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
     caf_gpu_system* s = f->sys;
@@ -259,12 +276,41 @@ void put_ref(caf_future* f) {  // mu not held
       delete f;
       return;
     }
-    std::lock_guard<std::mutex> g(s->mu);
-    if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
-    f->out = Block{};
-    f->pooled = true;
-    s->fut_pool.push_back(f);
+    caf_future* top = s->retired_futs.load(std::memory_order_relaxed);
+    do {
+      f->next_retired = top;
+    } while (!s->retired_futs.compare_exchange_weak(top, f, std::memory_order_release,
+                                                    std::memory_order_relaxed));
     if (s->waiters.load(std::memory_order_relaxed)) s->cv_space.notify_all();
+  }
+}
+
+// Returns retired slots and futures, with their arena blocks, to the pools
+// (mu held).  Both stacks are taken whole, so a push racing with this one
+// simply waits for the next call.
+void reclaim(caf_gpu_system* s) {
+  if (s->retired_slots.load(std::memory_order_relaxed)) {
+    uint32_t top = s->retired_slots.exchange(0, std::memory_order_acquire);
+    while (top) {
+      const uint32_t slot = top - 1;
+      SlotInfo& si = s->slots[slot];
+      top = si.next_retired;
+      for (uint32_t k = 0; k < si.ntemps; ++k) s->arena.free(si.temps[k].addr, si.temps[k].bytes);
+      si.ntemps = 0;
+      s->free_slots.push_back(slot);
+    }
+  }
+  if (s->retired_futs.load(std::memory_order_relaxed)) {
+    caf_future* f = s->retired_futs.exchange(nullptr, std::memory_order_acquire);
+    while (f) {
+      caf_future* next = f->next_retired;
+      if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
+      f->out = Block{};
+      f->next_retired = nullptr;
+      f->pooled = true;
+      s->fut_pool.push_back(f);
+      f = next;
+    }
   }
 }
 
@@ -318,28 +364,27 @@ void resolve_batch(caf_gpu_system* s, const Comp* recs, uint32_t n) {
   caf_future* futs[kPollBatch];
   const Comp* frec[kPollBatch];
   uint32_t nf = 0, valid = 0;
-  {
-    std::lock_guard<std::mutex> g(s->mu);
-    for (uint32_t i = 0; i < n; ++i) {
-      const Comp& c = recs[i];
-      const uint32_t slot = (uint32_t)(c.req_id & (kMaxSlots - 1));
-      if (slot >= s->cap || s->slots[slot].req_id != c.req_id) {
-        s->st_dup++;
-        continue;
-      }
-      SlotInfo& si = s->slots[slot];
-      for (uint32_t k = 0; k < si.ntemps; ++k) s->arena.free(si.temps[k].addr, si.temps[k].bytes);
-      si.ntemps = 0;
-      if (si.fut) {
-        futs[nf] = si.fut;
-        frec[nf] = &c;
-        ++nf;
-      }
-      si.fut = nullptr;
-      si.req_id = 0;
-      s->free_slots.push_back(slot);
-      ++valid;
+  // A slot's record was written under mu before its ring entry was
+  // published, and stays the poller's from its completion until reclaim()
+  // hands the slot out again; clearing req_id makes a repeated record for it
+  // a duplicate.
+  for (uint32_t i = 0; i < n; ++i) {
+    const Comp& c = recs[i];
+    const uint32_t slot = (uint32_t)(c.req_id & (kMaxSlots - 1));
+    if (slot >= s->cap || s->slots[slot].req_id != c.req_id) {
+      s->st_dup++;
+      continue;
     }
+    SlotInfo& si = s->slots[slot];
+    if (si.fut) {
+      futs[nf] = si.fut;
+      frec[nf] = &c;
+      ++nf;
+    }
+    si.fut = nullptr;
+    si.req_id = 0;
+    retire_slot(s, slot);
+    ++valid;
   }
   s->st_completions += valid;
   const int64_t t = now_ns();
@@ -648,6 +693,7 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   Block sout[1 + kMaxHops];
   uint32_t slot = 0;
   for (;;) {
+    reclaim(s);
     bool ok = !s->free_slots.empty();
     auto take = [&](uint64_t bytes, Block* b) {
       if (!ok) return;
@@ -1062,6 +1108,7 @@ int caf_gpu_drain(caf_gpu_system* s, int64_t timeout_ns) {
 int caf_gpu_get_stats(caf_gpu_system* s, caf_gpu_stats* o) {
   if (!s || !o) return CAF_E_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
+  reclaim(s);  // so that the arena figures count finished requests as freed
   o->requests = s->st_requests;
   o->sends = s->st_sends;
   o->completions = s->st_completions;
