@@ -109,8 +109,10 @@ struct alignas(128) DevCtl {
   uint32_t stop_seen;      // a drainer saw the host's stop flag
   uint32_t wg_exited[2];   // by launch parity: workgroups that left
   uint32_t retiring[2];    // by launch parity: generation that began to retire
-  uint8_t p5[100];
+  uint32_t backlog;        // the last drain pass left entries in the mailbox
+  uint8_t p5[96];
 };
+static_assert(sizeof(DevCtl) == 6 * 128, "hot counters on separate 128-byte lines");
 
 constexpr uint32_t kNopTile = 0xFFFFFFFFu;  // tile-map entry of a filler tile
 

@@ -227,22 +227,27 @@ __device__ __forceinline__ bool stage_done(KArgsC& a, const Desc& d, bool ring) 
 // workgroup's tile work is complete).  The last tile of a message resets
 // the slot's counters and completes or forwards it; returns true if the
 // workgroup is to run the next pipeline stage inline.
-__device__ __forceinline__ bool finish_tile(KArgsC& a, const Desc& d, uint32_t ntiles, bool ring) {
+// Counts `count` finished tiles of the message (thread 0).
+__device__ __forceinline__ bool finish_tiles(KArgsC& a, const Desc& d, uint32_t ntiles,
+                                             uint32_t count, bool ring) {
   const uint32_t slot = d.slot;
   SlotState* ss = &a.sstate[slot];
   bool cont = false;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  const uint32_t prev = __hip_atomic_fetch_add(&ss->done, 1u, __ATOMIC_RELAXED,
+  const uint32_t prev = __hip_atomic_fetch_add(&ss->done, count, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-  if (prev + 1 == ntiles) {
+  if (prev + count == ntiles) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     st_dev(&ss->done, 0u);
     st_dev(&ss->decision, 0u);
     cont = stage_done(a, d, ring);
   }
-  if (ring) __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELAXED,
+  if (ring) __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)count, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   return cont;
+}
+__device__ __forceinline__ bool finish_tile(KArgsC& a, const Desc& d, uint32_t ntiles, bool ring) {
+  return finish_tiles(a, d, ntiles, 1u, ring);
 }
 
 // ---- behaviour dispatch -----------------------------------------------------
@@ -268,6 +273,7 @@ __device__ __forceinline__ void hash_step(KArgsC& a, const Desc& d) {
 
 // kFull = false compiles every behaviour except GEMM: without the matrix
 // tiles the kernel needs far fewer registers and runs more waves per SIMD.
+// One tile of every behaviour except bf16 GEMM (see run_tiles).
 template <bool kFull>
 __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile, uint8_t* smem,
                          uint32_t* lds_ctr) {
@@ -278,18 +284,13 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
       break;
     case CAF_BHV_GEMM: {
       if constexpr (kFull) {
+        // bf16 products run through run_tiles (one call site keeps the
+        // tile inlined)
         float* C = reinterpret_cast<float*>(d.out);
-        if (d.flags & DF_BF16) {
-          const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
-          const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
-          if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
-          else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, (uint16_t*)smem);
-        } else {
-          const float* A = reinterpret_cast<const float*>(d.in0);
-          const float* B = reinterpret_cast<const float*>(d.in1);
-          if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, (float*)smem);
-          else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, (float*)smem);
-        }
+        const float* A = reinterpret_cast<const float*>(d.in0);
+        const float* B = reinterpret_cast<const float*>(d.in1);
+        if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, (float*)smem);
+        else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, (float*)smem);
       } else {
         // never reached: a light launch does not drain GEMM messages
         if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_DEVICE);
@@ -316,6 +317,28 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
     default:
       if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_INVALID);
       break;
+  }
+}
+
+// Tiles tile .. tile + count - 1 of one message (whole workgroup).  The
+// tiles of a bf16 GEMM run as one stream (the next tile's first slice loads
+// while the current one finishes); other behaviours run tile by tile.
+template <bool kFull>
+__device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t tile,
+                                          uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
+  if constexpr (kFull) {
+    if (d.behavior == CAF_BHV_GEMM && (d.flags & DF_BF16)) {
+      const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
+      const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
+      float* C = reinterpret_cast<float*>(d.out);
+      if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+      else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+      return;
+    }
+  }
+  for (uint32_t i = 0; i < count; ++i) {
+    if (i) __syncthreads();
+    run_tile<kFull>(a, d, tile + i, smem, lds_ctr);
   }
 }
 
@@ -389,7 +412,7 @@ plain_kernel(KArgs, Desc d, uint32_t ntiles) {
     s_dec = (dec == 1 && ld_dev(&ss->status) == CAF_OK) ? 1u : 0u;
   }
   __syncthreads();
-  if (s_dec) run_tile<kFull>(a, d, blockIdx.x, smem, &s_ctr);
+  if (s_dec) run_tiles<kFull>(a, d, blockIdx.x, 1u, smem, &s_ctr);
   __syncthreads();
   if (threadIdx.x == 0) finish_tile(a, d, ntiles, false);
 }
@@ -482,6 +505,8 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
     const uint64_t avail = tail - d;
     L.d = d;
     L.cnt = avail < a.max_batch ? avail : a.max_batch;
+    // Lets idle workgroups help while a backlog remains (relaxed: a hint).
+    st_dev(&a.dctl->backlog, avail > a.max_batch ? 1u : 0u);
     L.pub = ld_dev_acq(&a.dctl->tiles_pub);
     L.done = ld_dev_acq(&a.dctl->tiles_done);
     if (stop) st_dev(&a.dctl->stop_seen, 1u);
@@ -713,7 +738,14 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
       }
-      if (cmd == CMD_IDLE && lock_drain(a, false)) cmd = CMD_DRAIN;
+      // Draining an empty mailbox still holds the lock for a host round
+      // trip, so idle workgroups do not all poll it: the sentinels do, a
+      // workgroup that just finished work tries once, and so does one
+      // waiting for its reserved index to be published; everyone helps
+      // while the last pass left a backlog.
+      const bool may_drain = blockIdx.x < kSentinels || idle_rounds == 0 || c.next < c.end ||
+                             ld_dev(&a.dctl->backlog) != 0;
+      if (cmd == CMD_IDLE && may_drain && lock_drain(a, false)) cmd = CMD_DRAIN;
       s_cmd = cmd;
     }
     __syncthreads();
@@ -721,7 +753,7 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
     if (cmd == CMD_TILE) {
       const uint64_t g0 = s_g;
       const uint32_t nk = s_k;
-      for (uint32_t j = 0; j < nk; ++j) {
+      for (uint32_t j = 0; j < nk;) {
         const uint64_t g = g0 + j;
         if (t == 0) {
           const uint32_t slot = ld_dev(&a.tile2slot[g & (kTileMapCap - 1)]);
@@ -734,6 +766,7 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
             __hip_atomic_fetch_add(&a.dctl->tiles_done, (uint64_t)1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
           __syncthreads();
+          ++j;
           continue;
         }
         // The descriptor is the same for every lane: move it to scalar
@@ -747,15 +780,19 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
             dst[q] = __builtin_amdgcn_readfirstlane(src[q]);
         }
         const uint32_t ntiles = __builtin_amdgcn_readfirstlane(s_slot.ntiles);
-        const uint32_t tile = (uint32_t)(g - s_slot.tile_base);
+        const uint32_t tile = __builtin_amdgcn_readfirstlane((uint32_t)(g - s_slot.tile_base));
+        // The claimed indices that follow and still belong to this GEMM
+        // message run together, with one lookup and one completion count.
+        const uint32_t run = (kFull && d.behavior == CAF_BHV_GEMM) ? min(nk - j, ntiles - tile) : 1u;
         // A failed tile stops the message's other tiles; a one-tile message
         // cannot have failed before its tile runs.
         if (ntiles == 1 || ld_dev(&a.sstate[d.slot].status) == CAF_OK)
-          run_tile<kFull>(a, d, tile, smem, &s_ctr);
+          run_tiles<kFull>(a, d, tile, run, smem, &s_ctr);
         __syncthreads();
-        if (t == 0) s_cont = finish_tile(a, d, ntiles, true) ? 1u : 0u;
+        if (t == 0) s_cont = finish_tiles(a, d, ntiles, run, true) ? 1u : 0u;
         __syncthreads();
         if (s_cont) run_inline_stages(a, d.slot, &s_cont);
+        j += run;
       }
       last_work = now_ticks();
       idle_rounds = 0;
@@ -779,8 +816,10 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
       if (holding) {
         // Nobody may leave an index unexecuted: before this launch goes (or
         // once this workgroup has idled as long as a launch may linger),
-        // fill the outstanding reservations with filler tiles.
-        if ((leaving || now_ticks() - last_work > a.idle_ticks) && lock_drain(a, true)) {
+        // fill the outstanding reservations with filler tiles.  One lock
+        // attempt per round: spinning on it here would stop this workgroup
+        // from noticing that its index has been published meanwhile.
+        if ((leaving || now_ticks() - last_work > a.idle_ticks) && lock_drain(a, false)) {
           fill_reservations_locked(a);
           unlock_drain(a);
         }

@@ -325,23 +325,21 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
 // LDS load.  B is transposed on the way in: a thread loads a 4 (k) x 8 (n)
 // block as four 16-byte rows and regroups it in registers with byte
 // permutes into eight 8-byte columns.  smem: 2 x 2 x TE x (kBf16SliceK + 8)
-// bf16.
+// bf16.  One call computes `count` consecutive output tiles (row-major tile
+// order) of one product.
 // k per LDS slice of the bf16 tile: long enough that a slice's matrix-core
 // work covers the next slice's global loads.
 constexpr int kBf16SliceK = 64;
 
 template <int TE>
 __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
-                               float* __restrict__ C, uint32_t n, uint32_t tile,
-                               uint16_t* smem) {
+                               float* __restrict__ C, uint32_t n, uint32_t tile0,
+                               uint32_t count, uint16_t* smem) {
   constexpr int BK = kBf16SliceK;
   constexpr int LD = BK + 8;
   constexpr int WB = TE / 64;
   constexpr int QA = TE * BK / 8 / kThreads;  // 16-byte A chunks per thread
-  constexpr int NBB = (BK / 8) * (TE / 8);    // 8x8 B blocks per slice
   constexpr int SLICE = 2 * TE * LD;          // bf16 per LDS buffer
-  uint32_t tm, tn;
-  tile_coords(tile, n, TE, tm, tn);
   const auto Ag = global_ptr(A);
   const auto Bg = global_ptr(B);
   const auto Cg = global_ptr(C);
@@ -350,13 +348,22 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
   const bool vec = (n % 8u) == 0 && ((reinterpret_cast<uintptr_t>(A) |
                                       reinterpret_cast<uintptr_t>(B)) & 15u) == 0;
   floatx16 acc[WB][WB];
+  auto zero_acc = [&]() {
 #pragma unroll
-  for (int i = 0; i < WB; ++i)
+    for (int i = 0; i < WB; ++i)
 #pragma unroll
-    for (int j = 0; j < WB; ++j)
+      for (int j = 0; j < WB; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  };
+  auto store_tile = [&](uint32_t tm, uint32_t tn) {
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+      for (int j = 0; j < WB; ++j)
+        store_c<TE>(Cg, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
+                    acc[i][j]);
+  };
   auto mfma_slice = [&](const uint16_t* As, const uint16_t* Bs) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
@@ -379,54 +386,68 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   };
+  zero_acc();
 
   if (vec) {
-    // Per-thread sources, computed once per tile.  Rows of A and columns of
-    // B outside the matrix are clamped to valid ones instead of zeroed: they
-    // only feed rows / columns of C that are not stored.  k runs past n only
-    // in a partial last slice, which takes the checked loads (zeros).
+    // The tiles of the range run as one stream of 64-deep slices: while the
+    // matrix cores work on one slice, the next one (possibly the first of
+    // the next tile) is already being loaded, so a tile's first loads and
+    // its output stores overlap its neighbours' work.
+    //
+    // Every load is issued unconditionally from an address inside the
+    // matrix, so the registers it fills have a single definition and the
+    // compiler need not wait for the prefetch before the current slice's
+    // matrix instructions.  Rows of A and columns of B outside the matrix
+    // are clamped to valid ones: they only feed rows / columns of C that are
+    // not stored.  k runs past n only in a partial last slice; there the
+    // loads read clamped addresses and lstore() writes zeros instead.  With
+    // TE = 64 only half the threads own a B block; the others load a valid
+    // block and skip its store.
     constexpr int NB4 = (BK / 4) * (TE / 8);  // 4 (k) x 8 (n) blocks of B per slice
     static_assert(NB4 <= kThreads, "one B block per thread at most");
-    const uint32_t kb = t % (BK / 4), nb = t / (BK / 4);  // k-block fastest
-    const CAF_GLOBAL uint16_t* pa[QA];
+    const uint32_t kb = t % (BK / 4), nb = (t / (BK / 4)) % (TE / 8);  // k-block fastest
+    const bool has_b = NB4 == kThreads || t < (uint32_t)NB4;
     uint32_t kca[QA];
 #pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const uint32_t idx = t + kThreads * q;
-      const uint32_t row = idx / (BK / 8);
-      kca[q] = (idx % (BK / 8)) * 8;
-      const uint32_t gr = min(tm * TE + row, n - 1u);
-      pa[q] = Ag + (uint64_t)gr * n + kca[q];
-    }
-    uint32_t gcol = tn * TE + nb * 8;
-    if (gcol >= n) gcol = 0;
-    const CAF_GLOBAL uint16_t* pb = Bg + (uint64_t)(kb * 4) * n + gcol;
-    const bool has_b = t < (uint32_t)NB4;
+    for (int q = 0; q < QA; ++q) kca[q] = ((t + kThreads * q) % (BK / 8)) * 8;
+    const CAF_GLOBAL uint16_t* pa[QA];  // row starts of this thread's A chunks
+    const CAF_GLOBAL uint16_t* pb;      // column of this thread's B block
+    auto sources = [&](uint32_t tm, uint32_t tn) {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const uint32_t row = (t + kThreads * q) / (BK / 8);
+        pa[q] = Ag + (uint64_t)min(tm * TE + row, n - 1u) * n;
+      }
+      uint32_t gcol = tn * TE + nb * 8;
+      if (gcol >= n) gcol = 0;
+      pb = Bg + gcol;
+    };
     uint4 ra[QA], rb[4];
+    // checked: the slice at k0 may run past n (uniform)
     auto gload = [&](uint32_t k0, bool checked) {
-      if (!checked) {
 #pragma unroll
-        for (int q = 0; q < QA; ++q) ra[q] = load_global<uint4>(pa[q] + k0);
-        if (has_b) {
-          const CAF_GLOBAL uint16_t* p = pb + (uint64_t)k0 * n;
+      for (int q = 0; q < QA; ++q) {
+        // a chunk past the last k reads the row's first chunk instead
+        const uint32_t col = (!checked || k0 + kca[q] < n) ? k0 + kca[q] : 0u;
+        ra[q] = load_global<uint4>(pa[q] + col);
+      }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) rb[r] = load_global<uint4>(p + (uint64_t)r * n);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < QA; ++q)
-          ra[q] = (k0 + kca[q] < n) ? load_global<uint4>(pa[q] + k0) : make_uint4(0, 0, 0, 0);
-        if (has_b) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const uint32_t gk = k0 + kb * 4 + r;
-            rb[r] = gk < n ? load_global<uint4>(pb + (uint64_t)(k0 + r) * n)
-                           : make_uint4(0, 0, 0, 0);
-          }
-        }
+      for (int r = 0; r < 4; ++r) {
+        uint32_t row = k0 + kb * 4 + r;
+        row = checked ? min(row, n - 1u) : row;
+        rb[r] = load_global<uint4>(pb + (uint64_t)row * n);
       }
     };
-    auto lstore = [&](uint16_t* buf) {
+    auto lstore = [&](uint16_t* buf, uint32_t k0, bool checked) {
+      if (checked) {
+        const uint4 z = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < QA; ++q)
+          if (k0 + kca[q] >= n) ra[q] = z;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (k0 + kb * 4 + r >= n) rb[r] = z;
+      }
       uint16_t* As = buf;
       uint16_t* Bs = buf + TE * LD;
 #pragma unroll
@@ -451,44 +472,74 @@ __device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* _
         }
       }
     };
-    const uint32_t nk = (n + BK - 1) / BK;
-    const uint32_t last_checked = (n % BK) ? nk - 1 : nk;  // index of the partial slice, if any
-    gload(0, last_checked == 0);
-    lstore(smem);
+    const uint32_t nk = (n + BK - 1) / BK;   // slices per tile
+    const uint32_t last = nk - 1;            // the only slice that can be partial
+    const bool ragged = (n % BK) != 0;
+    const uint32_t steps = count * nk;
+    uint32_t tile = tile0, k = 0, tm, tn;
+    tile_coords(tile, n, TE, tm, tn);
+    sources(tm, tn);
+    gload(0, ragged && last == 0);
+    lstore(smem, 0, ragged && last == 0);
     __syncthreads();
     uint32_t cur = 0;
-    for (uint32_t k = 0; k < nk; ++k) {
-      const bool more = k + 1 < nk;
-      if (more) gload((k + 1) * BK, k + 1 == last_checked);
+    // Step s computes slice k of `tile` from LDS buffer `cur` and prefetches
+    // step s + 1.  The last step is peeled off so that every iteration
+    // issues its prefetch unconditionally.
+    for (uint32_t s = 0; s + 1 < steps; ++s) {
+      const bool tile_ends = k == last;
+      const uint32_t otm = tm, otn = tn;
+      const uint32_t k1 = tile_ends ? 0u : k + 1;
+      if (tile_ends) {
+        tile_coords(tile + 1, n, TE, tm, tn);
+        sources(tm, tn);
+      }
+      const bool chk = ragged && k1 == last;
+      gload(k1 * BK, chk);
+      // keep the prefetch ahead of the matrix instructions (the scheduler
+      // would otherwise sink the loads to shorten their registers' lives)
+      __builtin_amdgcn_sched_barrier(0);
       const uint16_t* buf = smem + cur * SLICE;
       mfma_slice(buf, buf + TE * LD);
-      if (more) lstore(smem + (cur ^ 1u) * SLICE);
+      if (tile_ends) {
+        store_tile(otm, otn);
+        zero_acc();
+        ++tile;
+      }
+      lstore(smem + (cur ^ 1u) * SLICE, k1 * BK, chk);
       __syncthreads();
       cur ^= 1u;
+      k = k1;
+    }
+    {
+      const uint16_t* buf = smem + cur * SLICE;
+      mfma_slice(buf, buf + TE * LD);
+      store_tile(tm, tn);
     }
   } else {
+    // ragged or unaligned operands: element loads, one buffer, tile by tile
     uint16_t* As = smem;
     uint16_t* Bs = smem + TE * LD;
-    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
-      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
-        const uint32_t row = idx / BK, kk = idx % BK;
-        const uint32_t gr = tm * TE + row, gk = k0 + kk;
-        As[row * LD + kk] = (gr < n && gk < n) ? Ag[(uint64_t)gr * n + gk] : (uint16_t)0;
-        const uint32_t kr = idx / TE, c = idx % TE;
-        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        Bs[c * LD + kr] = (gk2 < n && gc < n) ? Bg[(uint64_t)gk2 * n + gc] : (uint16_t)0;
+    for (uint32_t i = 0; i < count; ++i) {
+      uint32_t tm, tn;
+      tile_coords(tile0 + i, n, TE, tm, tn);
+      if (i) zero_acc();
+      for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+        for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
+          const uint32_t row = idx / BK, kk = idx % BK;
+          const uint32_t gr = tm * TE + row, gk = k0 + kk;
+          As[row * LD + kk] = (gr < n && gk < n) ? Ag[(uint64_t)gr * n + gk] : (uint16_t)0;
+          const uint32_t kr = idx / TE, c = idx % TE;
+          const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+          Bs[c * LD + kr] = (gk2 < n && gc < n) ? Bg[(uint64_t)gk2 * n + gc] : (uint16_t)0;
+        }
+        __syncthreads();
+        mfma_slice(As, Bs);
+        __syncthreads();
       }
-      __syncthreads();
-      mfma_slice(As, Bs);
-      __syncthreads();
+      store_tile(tm, tn);
     }
   }
-#pragma unroll
-  for (int i = 0; i < WB; ++i)
-#pragma unroll
-    for (int j = 0; j < WB; ++j)
-      store_c<TE>(Cg, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
-                  acc[i][j]);
 }
 
 // ---------------------------------------------------------------------------
