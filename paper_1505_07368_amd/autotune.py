@@ -44,16 +44,17 @@ def _store_cache(path, cache):
 
 
 def _time_drive(s, msgs, keep, window, reps):
+    """Median wall time of `reps` runs after a warm-up (the median, not the
+    minimum: candidates a few percent apart are otherwise ranked by luck)."""
     cg.drive_array(s, msgs, keep, window=window)  # warm-up
-    best = float("inf")
+    times = []
     for _ in range(reps):
         t = time.perf_counter()
         rc, _, st, _ = cg.drive_array(s, msgs, keep, window=window)
-        dt = time.perf_counter() - t
+        times.append(time.perf_counter() - t)
         if rc != cg.OK or not (st == cg.OK).all():
             return float("inf")
-        best = min(best, dt)
-    return best
+    return sorted(times)[len(times) // 2]
 
 
 def mandel_messages(actor, viewports, tile_rows=64, fp=cg.F32):
@@ -72,7 +73,7 @@ def mandel_messages(actor, viewports, tile_rows=64, fp=cg.F32):
     return msgs, args
 
 
-def tune_mandel(torch, viewports, mode="batched", cache_path=None, reps=2,
+def tune_mandel(torch, viewports, mode="batched", cache_path=None, reps=5,
                 pxs=(512, 1024, 2048, 4096), fp=cg.F32):
     """Returns {"mandel_tile_px": px, "grid": g} for the image workload."""
     key = f"{_device_name(torch)}|mandel|{mode}|fp{fp}|{len(viewports)}x" \
@@ -104,7 +105,7 @@ def tune_mandel(torch, viewports, mode="batched", cache_path=None, reps=2,
     return best
 
 
-def tune_gemm(torch, mode="batched", dtype="f32", count_per_size=256, cache_path=None, reps=2):
+def tune_gemm(torch, mode="batched", dtype="f32", count_per_size=256, cache_path=None, reps=5):
     """Returns the gemm_tile_class list (tile edge per size class)."""
     key = f"{_device_name(torch)}|gemm|{mode}|{dtype}|{count_per_size}"
     cache = _load_cache(cache_path)

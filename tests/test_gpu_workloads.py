@@ -251,6 +251,72 @@ def test_gemm_bench_batch_full_size(dtype):
         assert err <= 1e-5, (size, err)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gemm_ragged_runs_sampled(dtype):
+    """2048 requests with ragged n (72, 100, 136, 200, 264: partial last
+    k slice, both tile edges, n % 8 != 0 for 100) published in two drained
+    batches, so workgroups claim several consecutive tiles of one product and
+    run them as one stream.  Every output finite; 40 products spread over
+    the batch against the FP64 oracle."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    count = 2048
+    sizes = np.resize(np.array([72, 100, 136, 200, 264], np.int64), count)
+    nn = sizes * sizes
+    offs = np.concatenate([[0], np.cumsum(nn)[:-1]])
+    total = int(nn.sum())
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    A = torch.rand(total, generator=g, device="cuda") * 2 - 1
+    B = torch.rand(total, generator=g, device="cuda") * 2 - 1
+    code = cg.F32
+    if dtype == "bf16":
+        A, B, code = A.to(torch.bfloat16), B.to(torch.bfloat16), cg.BF16
+    C = torch.full((total,), float("nan"), device="cuda")
+    esz = A.element_size()
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=count, max_batch=1024)
+    try:
+        a = s.spawn(cg.BHV_GEMM)
+        args = np.zeros(count, cg.NP_GEMM)
+        args["n"] = sizes
+        args["in_dtype"] = code
+        bufs = np.zeros(2 * count, cg.NP_BUF)
+        bufs["data"][0::2] = A.data_ptr() + offs.astype(np.uint64) * esz
+        bufs["data"][1::2] = B.data_ptr() + offs.astype(np.uint64) * esz
+        bufs["numel"][0::2] = nn
+        bufs["numel"][1::2] = nn
+        bufs["dtype"] = code
+        bufs["on_device"] = 1
+        idx = np.arange(count, dtype=np.uint64)
+        msgs = np.zeros(count, cg.NP_MSG)
+        msgs["actor"] = a
+        msgs["n_in"] = 2
+        msgs["args"] = args.ctypes.data + idx * args.itemsize
+        msgs["args_bytes"] = args.itemsize
+        msgs["in_"] = bufs.ctypes.data + idx * 2 * bufs.itemsize
+        msgs["out"]["data"] = C.data_ptr() + offs.astype(np.uint64) * 4
+        msgs["out"]["numel"] = nn
+        msgs["out"]["dtype"] = cg.F32
+        msgs["out"]["on_device"] = 1
+        torch.cuda.synchronize()
+        rc, _, st, _ = cg.drive_array(s, msgs, (args, bufs, A, B, C), window=count)
+        assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+    finally:
+        s.shutdown()
+    assert torch.isfinite(C).all()
+    for i in np.linspace(0, count - 1, 40).astype(int):
+        size, o = int(sizes[i]), int(offs[i])
+        m = size * size
+        if dtype == "bf16":
+            Ah = A[o:o + m].view(torch.int16).cpu().numpy().view(np.uint16).reshape(size, size)
+            Bh = B[o:o + m].view(torch.int16).cpu().numpy().view(np.uint16).reshape(size, size)
+        else:
+            Ah = A[o:o + m].cpu().numpy().reshape(size, size)
+            Bh = B[o:o + m].cpu().numpy().reshape(size, size)
+        err = rel_fro(C[o:o + m].cpu().numpy().reshape(size, size), oracle.gemm(Ah, Bh, dtype))
+        assert err <= 1e-5, (int(i), size, err)
+
+
 def test_pipeline_bench_size_sampled():
     """The benchmark's pipeline leg at full size: 100,000 GEMM(128) -> tanh ->
     row-sum chains with device forwarding (persistent drain); every reply
