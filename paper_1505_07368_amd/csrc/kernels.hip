@@ -144,7 +144,7 @@ __device__ bool publish_tiles_locked(KArgsC& a, uint32_t slot, uint32_t nt) {
   return true;
 }
 
-__device__ bool lock_drain(KArgsC& a, bool bounded) {
+__device__ __forceinline__ bool lock_drain(KArgsC& a, bool bounded) {
   uint64_t t0 = now_ticks();
   for (;;) {
     uint32_t z = 0;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void hash_step(KArgsC& a, const Desc& d) {
 
 // kFull = false compiles every behaviour except GEMM: without the matrix
 // tiles the kernel needs far fewer registers and runs more waves per SIMD.
-// One tile of every behaviour except bf16 GEMM (see run_tiles).
+// One tile of every behaviour except GEMM (see run_tiles).
 template <bool kFull>
 __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile, uint8_t* smem,
                          uint32_t* lds_ctr) {
@@ -282,21 +282,11 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
       if (d.flags & DF_FP64) mandel_tile<double>(d, tile, lds_ctr);
       else mandel_tile<float>(d, tile, lds_ctr);
       break;
-    case CAF_BHV_GEMM: {
-      if constexpr (kFull) {
-        // bf16 products run through run_tiles (one call site keeps the
-        // tile inlined)
-        float* C = reinterpret_cast<float*>(d.out);
-        const float* A = reinterpret_cast<const float*>(d.in0);
-        const float* B = reinterpret_cast<const float*>(d.in1);
-        if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, (float*)smem);
-        else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, (float*)smem);
-      } else {
-        // never reached: a light launch does not drain GEMM messages
-        if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_DEVICE);
-      }
+    case CAF_BHV_GEMM:
+      // never reached: products run through run_tiles (one call site keeps
+      // the tiles inlined), and a light launch does not drain GEMM messages
+      if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_DEVICE);
       break;
-    }
     case CAF_BHV_TANH:
       tanh_tile(reinterpret_cast<const float*>(d.in0), reinterpret_cast<float*>(d.out),
                 (uint64_t)d.p.s.rows * d.p.s.cols, tile);
@@ -321,18 +311,25 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
 }
 
 // Tiles tile .. tile + count - 1 of one message (whole workgroup).  The
-// tiles of a bf16 GEMM run as one stream (the next tile's first slice loads
-// while the current one finishes); other behaviours run tile by tile.
+// tiles of a GEMM run as one stream (the next tile's first slice loads while
+// the current one finishes); other behaviours run tile by tile.
 template <bool kFull>
 __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t tile,
                                           uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
   if constexpr (kFull) {
-    if (d.behavior == CAF_BHV_GEMM && (d.flags & DF_BF16)) {
-      const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
-      const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
+    if (d.behavior == CAF_BHV_GEMM) {
       float* C = reinterpret_cast<float*>(d.out);
-      if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
-      else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+      if (d.flags & DF_BF16) {
+        const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
+        const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
+        if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+        else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+      } else {
+        const float* A = reinterpret_cast<const float*>(d.in0);
+        const float* B = reinterpret_cast<const float*>(d.in1);
+        if (d.tcfg == 128) gemm_f32_tile<128>(A, B, C, d.p.g.n, tile, count, (float*)smem);
+        else gemm_f32_tile<64>(A, B, C, d.p.g.n, tile, count, (float*)smem);
+      }
       return;
     }
   }

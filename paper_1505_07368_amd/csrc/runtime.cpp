@@ -14,9 +14,10 @@
 // Concurrency: one mutex (`mu`) guards the actor table, the slot pool, the
 // arena and the ring writer; a request takes it once in the common case.
 // The poller never takes it: finished slots and unreferenced futures go onto
-// two lock-free stacks, which the next holder of the mutex empties into the
-// slot pool, the future pool and the arena.  (A contended mutex hand-off
-// costs the poller a sleep and a wake-up per batch of completions.)
+// two lock-free stacks, and each later request returns a few of them to the
+// slot pool, the future pool and the arena (all of them when it would
+// otherwise be refused).  A contended mutex hand-off costs the poller a
+// sleep and a wake-up per batch of completions.
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
@@ -30,6 +31,7 @@
 #include <mutex>
 #include <set>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "caf_internal.h"
@@ -55,8 +57,12 @@ inline int64_t now_ns() {
       .count();
 }
 
-// Best-fit sub-allocator over the caller's arena, with coalescing.  Not
-// synchronised: every call is made with the system mutex held.
+// Best-fit sub-allocator over the caller's arena, with coalescing.  Freed
+// blocks first go onto per-size lists that the next request of that size
+// takes in O(1) (serving workloads repeat a few sizes); they are merged
+// into the coalescing tree when a request finds no block, so a request
+// fails only if the coalesced arena cannot hold it.  Not synchronised:
+// every call is made with the system mutex held.
 class Arena {
  public:
   void init(uint64_t base, uint64_t bytes) {
@@ -64,6 +70,8 @@ class Arena {
     size_ = bytes / kGranule * kGranule;
     by_off_.clear();
     by_size_.clear();
+    quick_.clear();
+    quick_blocks_ = 0;
     insert(0, size_);
   }
   static uint64_t granules(uint64_t bytes) {
@@ -72,19 +80,47 @@ class Arena {
   }
   bool alloc(uint64_t bytes, uint64_t* addr) {
     const uint64_t need = granules(bytes);
+    auto q = quick_.find(need);
+    if (q != quick_.end() && !q->second.empty()) {
+      *addr = base_ + q->second.back();
+      q->second.pop_back();
+      --quick_blocks_;
+    } else if (!tree_alloc(need, addr)) {
+      if (!quick_blocks_) return false;
+      flush_quick();
+      if (!tree_alloc(need, addr)) return false;
+    }
+    in_use_ += need;
+    if (in_use_ > peak_) peak_ = in_use_;
+    return true;
+  }
+  void free(uint64_t addr, uint64_t bytes) {
+    const uint64_t sz = granules(bytes);
+    in_use_ -= sz;
+    quick_[sz].push_back(addr - base_);
+    if (++quick_blocks_ > kQuickMax) flush_quick();
+  }
+  uint64_t in_use() const { return in_use_; }
+  uint64_t peak() const { return peak_; }
+
+ private:
+  static constexpr uint64_t kQuickMax = 1u << 16;
+  bool tree_alloc(uint64_t need, uint64_t* addr) {
     auto it = by_size_.lower_bound({need, 0});
     if (it == by_size_.end()) return false;
     const uint64_t sz = it->first, off = it->second;
     erase(off, sz);
     if (sz > need) insert(off + need, sz - need);
-    in_use_ += need;
-    if (in_use_ > peak_) peak_ = in_use_;
     *addr = base_ + off;
     return true;
   }
-  void free(uint64_t addr, uint64_t bytes) {
-    uint64_t off = addr - base_, sz = granules(bytes);
-    in_use_ -= sz;
+  void flush_quick() {
+    for (auto& kv : quick_)
+      for (uint64_t off : kv.second) tree_free(off, kv.first);
+    quick_.clear();
+    quick_blocks_ = 0;
+  }
+  void tree_free(uint64_t off, uint64_t sz) {
     auto nx = by_off_.lower_bound(off);
     if (nx != by_off_.end() && nx->first == off + sz) {
       const uint64_t nsz = nx->second;
@@ -103,10 +139,6 @@ class Arena {
     }
     insert(off, sz);
   }
-  uint64_t in_use() const { return in_use_; }
-  uint64_t peak() const { return peak_; }
-
- private:
   void insert(uint64_t off, uint64_t sz) {
     by_off_[off] = sz;
     by_size_.emplace(sz, off);
@@ -118,6 +150,8 @@ class Arena {
   uint64_t base_ = 0, size_ = 0, in_use_ = 0, peak_ = 0;
   std::map<uint64_t, uint64_t> by_off_;                 // free blocks by offset
   std::set<std::pair<uint64_t, uint64_t>> by_size_;     // (size, offset): best fit, lowest offset
+  std::unordered_map<uint64_t, std::vector<uint64_t>> quick_;  // size -> freed offsets
+  uint64_t quick_blocks_ = 0;
 };
 
 struct Block {
@@ -214,6 +248,8 @@ struct caf_gpu_system {
   // Returned without mu: pushed by any thread, emptied whole under mu.
   std::atomic<uint32_t> retired_slots{0};  // slot + 1 of the top entry, 0 if empty
   std::atomic<caf_future*> retired_futs{nullptr};
+  std::vector<uint32_t> pend_slots;        // taken off the stacks, not yet returned (mu)
+  std::vector<caf_future*> pend_futs;
   // drain kernel
   std::mutex launch_mu;
   std::atomic<uint32_t> launched_gen{0};
@@ -285,32 +321,51 @@ void put_ref(caf_future* f) {  // mu not held
   }
 }
 
-// Returns retired slots and futures, with their arena blocks, to the pools
-// (mu held).  Both stacks are taken whole, so a push racing with this one
-// simply waits for the next call.
-void reclaim(caf_gpu_system* s) {
+// Returns up to `budget` retired slots and as many futures, with their
+// arena blocks, to the pools (mu held).  Both stacks are taken whole into
+// pending lists, so a push racing with this one simply waits for the next
+// call; the budget spreads the work of a large burst of completions over
+// the requests that follow instead of stalling one of them.
+constexpr size_t kReclaimBudget = 16;
+constexpr size_t kReclaimAll = ~size_t(0);
+
+bool reclaim_pending(const caf_gpu_system* s) {
+  return !s->pend_slots.empty() || !s->pend_futs.empty() ||
+         s->retired_slots.load(std::memory_order_relaxed) ||
+         s->retired_futs.load(std::memory_order_relaxed);
+}
+
+void reclaim(caf_gpu_system* s, size_t budget) {
   if (s->retired_slots.load(std::memory_order_relaxed)) {
     uint32_t top = s->retired_slots.exchange(0, std::memory_order_acquire);
     while (top) {
-      const uint32_t slot = top - 1;
-      SlotInfo& si = s->slots[slot];
-      top = si.next_retired;
-      for (uint32_t k = 0; k < si.ntemps; ++k) s->arena.free(si.temps[k].addr, si.temps[k].bytes);
-      si.ntemps = 0;
-      s->free_slots.push_back(slot);
+      s->pend_slots.push_back(top - 1);
+      top = s->slots[top - 1].next_retired;
     }
   }
   if (s->retired_futs.load(std::memory_order_relaxed)) {
     caf_future* f = s->retired_futs.exchange(nullptr, std::memory_order_acquire);
     while (f) {
-      caf_future* next = f->next_retired;
-      if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
-      f->out = Block{};
-      f->next_retired = nullptr;
-      f->pooled = true;
-      s->fut_pool.push_back(f);
-      f = next;
+      s->pend_futs.push_back(f);
+      f = f->next_retired;
     }
+  }
+  for (size_t n = 0; n < budget && !s->pend_slots.empty(); ++n) {
+    const uint32_t slot = s->pend_slots.back();
+    s->pend_slots.pop_back();
+    SlotInfo& si = s->slots[slot];
+    for (uint32_t k = 0; k < si.ntemps; ++k) s->arena.free(si.temps[k].addr, si.temps[k].bytes);
+    si.ntemps = 0;
+    s->free_slots.push_back(slot);
+  }
+  for (size_t n = 0; n < budget && !s->pend_futs.empty(); ++n) {
+    caf_future* f = s->pend_futs.back();
+    s->pend_futs.pop_back();
+    if (f->out.bytes) s->arena.free(f->out.addr, f->out.bytes);
+    f->out = Block{};
+    f->next_retired = nullptr;
+    f->pooled = true;
+    s->fut_pool.push_back(f);
   }
 }
 
@@ -692,8 +747,9 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   Block staged[2];
   Block sout[1 + kMaxHops];
   uint32_t slot = 0;
+  bool reclaim_all = false;
   for (;;) {
-    reclaim(s);
+    reclaim(s, reclaim_all ? kReclaimAll : kReclaimBudget);
     bool ok = !s->free_slots.empty();
     auto take = [&](uint64_t bytes, Block* b) {
       if (!ok) return;
@@ -722,6 +778,10 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
       if (b.bytes) s->arena.free(b.addr, b.bytes), b = Block{};
     for (auto& b : sout)
       if (b.bytes) s->arena.free(b.addr, b.bytes), b = Block{};
+    if (!reclaim_all && reclaim_pending(s)) {
+      reclaim_all = true;  // everything finished goes back before refusing
+      continue;
+    }
     if (!s->cfg.blocking) {
       s->st_rejected++;
       return CAF_E_OVERLOAD;
@@ -1108,7 +1168,7 @@ int caf_gpu_drain(caf_gpu_system* s, int64_t timeout_ns) {
 int caf_gpu_get_stats(caf_gpu_system* s, caf_gpu_stats* o) {
   if (!s || !o) return CAF_E_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
-  reclaim(s);  // so that the arena figures count finished requests as freed
+  reclaim(s, kReclaimAll);  // so that the arena figures count finished requests as freed
   o->requests = s->st_requests;
   o->sends = s->st_sends;
   o->completions = s->st_completions;

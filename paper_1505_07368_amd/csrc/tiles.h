@@ -207,16 +207,17 @@ __device__ __forceinline__ void store_c(CAF_GLOBAL float* C, uint32_t n, uint32_
 // other LDS buffer), so one barrier per slice suffices.
 
 // fp32 inputs: v_mfma_f32_32x32x2f32, k slices of 16; LDS A k-major
-// (transposed on store), B row-major.  smem: 2 x 2 x 16 x TE floats.
+// (transposed on store), B row-major.  smem: 2 x 2 x 16 x TE floats.  One
+// call computes `count` consecutive output tiles (row-major tile order) of
+// one product, as one stream of slices like the bf16 tile below.
 template <int TE>
-__device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restrict__ B,
-                              float* __restrict__ C, uint32_t n, uint32_t tile, float* smem) {
+__device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ A, const float* __restrict__ B,
+                              float* __restrict__ C, uint32_t n, uint32_t tile0,
+                              uint32_t count, float* smem) {
   constexpr int BK = 16;
   constexpr int WB = TE / 64;               // 32x32 blocks per wave and dimension
   constexpr int Q = TE * BK / 4 / kThreads; // float4 per thread and operand
   constexpr int SLICE = 2 * BK * TE;        // floats per LDS buffer
-  uint32_t tm, tn;
-  tile_coords(tile, n, TE, tm, tn);
   const auto Ag = global_ptr(A);
   const auto Bg = global_ptr(B);
   const auto Cg = global_ptr(C);
@@ -225,13 +226,22 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
   const bool vec = (n % 4u) == 0 && ((reinterpret_cast<uintptr_t>(A) |
                                       reinterpret_cast<uintptr_t>(B)) & 15u) == 0;
   floatx16 acc[WB][WB];
+  auto zero_acc = [&]() {
 #pragma unroll
-  for (int i = 0; i < WB; ++i)
+    for (int i = 0; i < WB; ++i)
 #pragma unroll
-    for (int j = 0; j < WB; ++j)
+      for (int j = 0; j < WB; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  };
+  auto store_tile = [&](uint32_t tm, uint32_t tn) {
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+      for (int j = 0; j < WB; ++j)
+        store_c<TE>(Cg, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
+                    acc[i][j]);
+  };
   auto mfma_slice = [&](const float* As, const float* Bs) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
@@ -248,10 +258,13 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   };
+  zero_acc();
 
   if (vec) {
+    // Per-lane zero fill at the edges: a load outside the matrix is not
+    // issued and its registers hold zeros.
     float4 ra[Q], rb[Q];
-    auto gload = [&](uint32_t k0) {
+    auto gload = [&](uint32_t tm, uint32_t tn, uint32_t k0) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const uint32_t idx = t + kThreads * q;
@@ -280,43 +293,61 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
         *reinterpret_cast<float4*>(Bs + kr * TE + c) = rb[q];
       }
     };
-    gload(0);
+    const uint32_t nk = (n + BK - 1) / BK;  // slices per tile
+    const uint32_t steps = count * nk;
+    uint32_t tile = tile0, k = 0, tm, tn;
+    tile_coords(tile, n, TE, tm, tn);
+    gload(tm, tn, 0);
     lstore(smem);
     __syncthreads();
     uint32_t cur = 0;
-    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
-      const bool more = k0 + BK < n;
-      if (more) gload(k0 + BK);
+    for (uint32_t s = 0; s + 1 < steps; ++s) {
+      const bool tile_ends = k + 1 == nk;
+      const uint32_t otm = tm, otn = tn;
+      const uint32_t k1 = tile_ends ? 0u : k + 1;
+      if (tile_ends) tile_coords(tile + 1, n, TE, tm, tn);
+      gload(tm, tn, k1 * BK);
       const float* buf = smem + cur * SLICE;
       mfma_slice(buf, buf + BK * TE);
-      if (more) lstore(smem + (cur ^ 1u) * SLICE);
+      if (tile_ends) {
+        store_tile(otm, otn);
+        zero_acc();
+        ++tile;
+      }
+      lstore(smem + (cur ^ 1u) * SLICE);
       __syncthreads();
       cur ^= 1u;
+      k = k1;
+    }
+    {
+      const float* buf = smem + cur * SLICE;
+      mfma_slice(buf, buf + BK * TE);
+      store_tile(tm, tn);
     }
   } else {
-    // ragged or unaligned operands: element loads, one buffer
+    // ragged or unaligned operands: element loads, one buffer, tile by tile
     float* As = smem;
     float* Bs = smem + BK * TE;
-    for (uint32_t k0 = 0; k0 < n; k0 += BK) {
-      for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
-        const uint32_t row = idx / BK, kk = idx % BK;
-        const uint32_t gr = tm * TE + row, gk = k0 + kk;
-        As[kk * TE + row] = (gr < n && gk < n) ? Ag[(uint64_t)gr * n + gk] : 0.f;
-        const uint32_t kr = idx / TE, c = idx % TE;
-        const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
-        Bs[kr * TE + c] = (gk2 < n && gc < n) ? Bg[(uint64_t)gk2 * n + gc] : 0.f;
+    for (uint32_t i = 0; i < count; ++i) {
+      uint32_t tm, tn;
+      tile_coords(tile0 + i, n, TE, tm, tn);
+      if (i) zero_acc();
+      for (uint32_t k0 = 0; k0 < n; k0 += BK) {
+        for (uint32_t idx = t; idx < (uint32_t)(TE * BK); idx += kThreads) {
+          const uint32_t row = idx / BK, kk = idx % BK;
+          const uint32_t gr = tm * TE + row, gk = k0 + kk;
+          As[kk * TE + row] = (gr < n && gk < n) ? Ag[(uint64_t)gr * n + gk] : 0.f;
+          const uint32_t kr = idx / TE, c = idx % TE;
+          const uint32_t gk2 = k0 + kr, gc = tn * TE + c;
+          Bs[kr * TE + c] = (gk2 < n && gc < n) ? Bg[(uint64_t)gk2 * n + gc] : 0.f;
+        }
+        __syncthreads();
+        mfma_slice(As, Bs);
+        __syncthreads();
       }
-      __syncthreads();
-      mfma_slice(As, Bs);
-      __syncthreads();
+      store_tile(tm, tn);
     }
   }
-#pragma unroll
-  for (int i = 0; i < WB; ++i)
-#pragma unroll
-    for (int j = 0; j < WB; ++j)
-      store_c<TE>(Cg, n, tm * TE + wm * (TE / 2) + i * 32, tn * TE + wn * (TE / 2) + j * 32,
-                  acc[i][j]);
 }
 
 // bfloat16 inputs: v_mfma_f32_32x32x16_bf16, k slices of kBf16SliceK.  Both operands
@@ -332,7 +363,7 @@ __device__ void gemm_f32_tile(const float* __restrict__ A, const float* __restri
 constexpr int kBf16SliceK = 64;
 
 template <int TE>
-__device__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+__device__ __forceinline__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
                                float* __restrict__ C, uint32_t n, uint32_t tile0,
                                uint32_t count, uint16_t* smem) {
   constexpr int BK = kBf16SliceK;
