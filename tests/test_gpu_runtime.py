@@ -177,6 +177,48 @@ def test_nonblocking_admission_overload():
         assert f4.wait(30)[0] == cg.OK
 
 
+def test_arena_reuse_then_coalesce():
+    """Replies in the arena: freed blocks are reused by size, merged when a
+    larger reply needs the space, and a reply larger than the arena is
+    refused without blocking."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode="batched", arena_bytes=16 << 20, ring_slots=64, blocking=False) as s:
+        g = s.spawn(cg.BHV_GEMM)
+        A, B = gen.gemm_pair(21, 512)
+        At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        A2, B2 = gen.gemm_pair(22, 1024)
+        At2, Bt2 = torch.from_numpy(A2).cuda(), torch.from_numpy(B2).cuda()
+        torch.cuda.synchronize()
+        for _ in range(2):  # the second round reuses the freed 1 MB blocks
+            futs = [s.request(g, cg.caf_gemm_args(512, cg.F32), inputs=[At, Bt])
+                    for _ in range(12)]
+            outs = [f.result() for f in futs]
+            assert all(st == cg.OK for st, _ in outs)
+            err = rel_fro(outs[-1][1].cpu().numpy().reshape(512, 512), oracle.gemm(A, B))
+            assert err <= 1e-5, err
+            for f in futs:
+                f.release()
+            assert s.drain(30) == cg.OK
+            assert s.stats()["arena_in_use"] == 0
+        # 2 x 4 MB replies only fit once the freed 1 MB blocks are merged
+        futs = [s.request(g, cg.caf_gemm_args(1024, cg.F32), inputs=[At2, Bt2])
+                for _ in range(2)]
+        outs = [f.result() for f in futs]
+        assert all(st == cg.OK for st, _ in outs)
+        err = rel_fro(outs[0][1].cpu().numpy().reshape(1024, 1024), oracle.gemm(A2, B2))
+        assert err <= 1e-5, err
+        assert s.stats()["arena_in_use"] == 8 << 20
+        for f in futs:
+            f.release()
+        assert s.drain(30) == cg.OK
+        # a 17.6 MB reply (n = 2100) cannot fit a 16 MiB arena
+        A3 = torch.zeros(2100 * 2100, device="cuda")
+        rc, f3 = s.request_raw(g, cg.caf_gemm_args(2100, cg.F32), inputs=[A3, A3])
+        assert rc == cg.E_OVERLOAD and f3 is None
+        assert s.stats()["arena_in_use"] == 0
+
+
 @pytest.mark.parametrize("n,chains", [(128, 24), (512, 3)])
 def test_pipeline_device_vs_host_forwarding(sysm, n, chains):
     """n = 128: the tanh and row-sum stages are small enough to run in the
