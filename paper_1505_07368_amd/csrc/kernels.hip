@@ -714,10 +714,18 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
   __shared__ __align__(16) DevSlot s_slot;
   __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop, s_cont;
   __shared__ uint64_t s_g;
+  // sentinel: the published and drained counts last seen, and since when
+  // they have not moved (thread 0; kept in LDS, not in registers)
+  __shared__ uint64_t s_seen_pub, s_seen_drained, s_still_since;
   const uint32_t t = threadIdx.x;
   uint64_t last_work = now_ticks();
   uint32_t idle_rounds = 0;
   Claim c;  // thread 0's reservation
+  if (t == 0) {
+    s_seen_pub = ~0ull;
+    s_seen_drained = ~0ull;
+    s_still_since = last_work;
+  }
   for (;;) {
     if (t == 0) {
       uint32_t cmd = CMD_IDLE;
@@ -822,18 +830,29 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         }
       } else if (leaving) {
         ex = 1;
-      } else if (blockIdx.x < kSentinels && now_ticks() - last_work > a.idle_ticks &&
-                 ld_dev(&a.dctl->tiles_claimed) >= ld_dev(&a.dctl->tiles_pub) &&
-                 ld_dev(&a.dctl->drain_lock) == 0 &&
-                 ld_sys_acq(&a.hctl->tail) == ld_dev_acq(&a.dctl->drained)) {
-        // Idle long enough with an empty mailbox: retire this launch.  Every
-        // workgroup of it leaves once it holds no work (claimed tiles are
-        // finished first), and the host starts a new launch when messages
-        // arrive.  Batched mode lingers a few tens of microseconds,
-        // persistent mode much longer.
-        st_dev(&a.dctl->retiring[par], a.gen);
-        st_sys_rel(&a.hctl->retiring[par], a.gen);
-        ex = 1;
+      } else if (blockIdx.x < kSentinels && now_ticks() - last_work > a.idle_ticks) {
+        // The system counts as idle once neither the published tile count
+        // nor the drained count has moved for the linger time (this
+        // sentinel's own last work says nothing about the others').
+        const uint64_t pubv = ld_dev(&a.dctl->tiles_pub);
+        const uint64_t drv = ld_dev_acq(&a.dctl->drained);
+        const uint64_t now = now_ticks();
+        if (pubv != s_seen_pub || drv != s_seen_drained) {
+          s_seen_pub = pubv;
+          s_seen_drained = drv;
+          s_still_since = now;
+        } else if (now - s_still_since > a.idle_ticks &&
+                   ld_dev(&a.dctl->tiles_claimed) >= pubv && ld_dev(&a.dctl->drain_lock) == 0 &&
+                   ld_sys_acq(&a.hctl->tail) == drv) {
+          // Idle long enough with an empty mailbox: retire this launch.
+          // Every workgroup of it leaves once it holds no work (claimed
+          // tiles are finished first), and the host starts a new launch when
+          // messages arrive.  Batched mode lingers a few tens of
+          // microseconds, persistent mode much longer.
+          st_dev(&a.dctl->retiring[par], a.gen);
+          st_sys_rel(&a.hctl->retiring[par], a.gen);
+          ex = 1;
+        }
       }
       s_exit = ex;
       if (!ex) {
