@@ -177,6 +177,23 @@ def test_nonblocking_admission_overload():
         assert f4.wait(30)[0] == cg.OK
 
 
+def test_batched_pingpong_keeps_its_launch():
+    """Window-1 ping-pong in batched mode (default 50 us linger): the drain
+    launch stays up between requests instead of retiring in every gap (a
+    sentinel once judged idleness by its own last work alone, which
+    relaunched the kernel for about 13% of the requests)."""
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode="batched", arena_bytes=64 << 20, ring_slots=256) as s:
+        a = s.spawn(cg.BHV_NOOP)
+        x = np.array([7], np.int32)
+        msgs = [{"actor": a, "inputs": [x]} for _ in range(1000)]
+        s.drive(msgs[:50], window=1)
+        before = s.stats()["drain_launches"]
+        rc, _, st, _ = s.drive(msgs, window=1)
+        assert rc == cg.OK and (st == cg.OK).all()
+        assert s.stats()["drain_launches"] - before <= 50
+
+
 def test_arena_reuse_then_coalesce():
     """Replies in the arena: freed blocks are reused by size, merged when a
     larger reply needs the space, and a reply larger than the arena is
