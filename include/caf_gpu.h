@@ -281,6 +281,45 @@ int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t count, uint
                   const int64_t* arrival_ns, uint32_t chain_hops, const caf_actor* hop_actor,
                   int64_t* latency_ns, int32_t* status, double* elapsed_s);
 
+/* ---- CPU actors and the CPU+GPU split (Sec. 7.5) ------------------------
+ * The paper's offload experiment computes one Mandelbrot image partly on
+ * CPU actors and partly on a GPU compute actor and times the whole image as
+ * the GPU's share grows.  These two calls are that experiment; the GPU path
+ * never calls them.
+ *
+ * caf_cpu_mandel_rows: the CPU actors' kernel on the calling thread.  Global
+ * rows [row_begin, row_end) of the image `a` describes (a->row0 and a->rows
+ * are not used) are written to out_host, uint16 [row_end - row_begin][width]
+ * row-major, caller-owned.  The counts equal the GPU behaviour's (same
+ * recurrence, operation order and rounding).  Needs no device.  Returns
+ * CAF_E_INVALID for a NULL pointer, a bad width, height, max_iter or fp, or
+ * rows outside the image.
+ *
+ * caf_offload_mandel: the whole image `image` (row0 = 0, rows = height).
+ * Rows [0, gpu_rows) go to `gpu_actor` (a Mandelbrot actor) as requests of
+ * at most 64 rows whose replies are written into dev_stage (device memory,
+ * at least gpu_rows * width uint16, caller-owned) and then copied to
+ * out_host; at the same time rows [gpu_rows, height) are computed by
+ * `cpu_threads` worker threads of the system (0 = one per hardware thread;
+ * the pool is created on first use and kept until caf_gpu_shutdown).
+ * out_host: uint16 [height][width], caller-owned host memory.  times
+ * (optional): wall time of the call, and when each share was complete in
+ * host memory, from the start of the call.  Calls on one system run one at
+ * a time.  Returns CAF_OK, CAF_E_INVALID for bad arguments, a call-time
+ * error of a request, the first error reply, or CAF_E_DEVICE if the copy
+ * fails. */
+typedef struct {
+  int64_t total_ns;
+  int64_t gpu_done_ns; /* the GPU share in out_host (0 if gpu_rows = 0) */
+  int64_t cpu_done_ns; /* the CPU share in out_host (0 if gpu_rows = height) */
+} caf_offload_times;
+
+int caf_cpu_mandel_rows(const caf_mandel_args* a, uint32_t row_begin, uint32_t row_end,
+                        uint16_t* out_host);
+int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor, const caf_mandel_args* image,
+                       uint32_t gpu_rows, uint32_t cpu_threads, uint16_t* dev_stage,
+                       uint16_t* out_host, caf_offload_times* times);
+
 #ifdef __cplusplus
 }
 #endif

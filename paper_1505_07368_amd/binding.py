@@ -28,7 +28,8 @@ MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "persistent": MODE_PERSIS
 EXPORTED = ["caf_gpu_init", "caf_gpu_spawn", "caf_gpu_send", "caf_gpu_request",
             "caf_future_wait", "caf_future_poll", "caf_future_id", "caf_future_release",
             "caf_gpu_quit", "caf_gpu_drain", "caf_gpu_shutdown", "caf_gpu_strerror",
-            "caf_gpu_get_stats", "caf_gpu_drain_kernel_ms", "caf_gpu_drive"]
+            "caf_gpu_get_stats", "caf_gpu_drain_kernel_ms", "caf_gpu_drive",
+            "caf_cpu_mandel_rows", "caf_offload_mandel"]
 
 
 class caf_buf(C.Structure):
@@ -55,6 +56,10 @@ class caf_mandel_args(C.Structure):
 
 class caf_gemm_args(C.Structure):
     _fields_ = [("n", C.c_uint32), ("in_dtype", C.c_int32)]
+
+
+class caf_offload_times(C.Structure):
+    _fields_ = [("total_ns", C.c_int64), ("gpu_done_ns", C.c_int64), ("cpu_done_ns", C.c_int64)]
 
 
 class caf_shape_args(C.Structure):
@@ -113,6 +118,9 @@ def load():
         "caf_gpu_drain_kernel_ms": ([vp, P(u64)], C.c_double),
         "caf_gpu_drive": ([vp, P(caf_msg), u64, u32, vp, u32, vp, vp, vp, P(C.c_double)],
                           C.c_int),
+        "caf_cpu_mandel_rows": ([P(caf_mandel_args), u32, u32, vp], C.c_int),
+        "caf_offload_mandel": ([vp, u64, P(caf_mandel_args), u32, u32, vp, vp,
+                                P(caf_offload_times)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -124,6 +132,16 @@ def load():
 
 def strerror(st: int) -> str:
     return load().caf_gpu_strerror(st).decode()
+
+
+def cpu_mandel_rows(args: "caf_mandel_args", row_begin: int, row_end: int) -> np.ndarray:
+    """caf_cpu_mandel_rows: rows [row_begin, row_end) of the image on the
+    calling thread (the CPU actors' kernel); uint16 [rows, width]."""
+    out = np.zeros((row_end - row_begin, args.width), np.uint16)
+    st = load().caf_cpu_mandel_rows(C.byref(args), row_begin, row_end, out.ctypes.data)
+    if st != OK:
+        raise CafError("caf_cpu_mandel_rows", st)
+    return out
 
 
 class CafError(RuntimeError):
@@ -295,6 +313,32 @@ class System:
         n = C.c_uint64()
         ms = self.L.caf_gpu_drain_kernel_ms(self.h, C.byref(n))
         return ms, n.value
+
+    def offload_mandel(self, actor, image: "caf_mandel_args", gpu_rows: int, cpu_threads=0,
+                       stage=None, out=None):
+        """caf_offload_mandel: the image with rows [0, gpu_rows) on `actor`
+        and the rest on the CPU actors.  Returns (uint16 [height, width],
+        times dict in ns).  `stage` (device uint16 tensor of at least
+        gpu_rows * width) and `out` (host uint16 array) may be given to reuse
+        buffers."""
+        torch = _torch()
+        if out is None:
+            out = np.zeros((image.height, image.width), np.uint16)
+        assert out.dtype == np.uint16 and out.flags.c_contiguous
+        assert out.size >= image.height * image.width
+        if gpu_rows and stage is None:
+            stage = torch.empty(gpu_rows * image.width, dtype=torch.uint16, device="cuda")
+        if gpu_rows:
+            assert stage.dtype == torch.uint16 and stage.is_cuda
+            assert stage.numel() >= gpu_rows * image.width
+        t = caf_offload_times()
+        st = self.L.caf_offload_mandel(self.h, actor, C.byref(image), gpu_rows, cpu_threads,
+                                       stage.data_ptr() if gpu_rows else None,
+                                       out.ctypes.data, C.byref(t))
+        if st != OK:
+            raise CafError("caf_offload_mandel", st)
+        return out, {"total_ns": t.total_ns, "gpu_done_ns": t.gpu_done_ns,
+                     "cpu_done_ns": t.cpu_done_ns}
 
     def view(self, res: caf_buf):
         """The reply buffer as a tensor (device, a view into the arena or the

@@ -15,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcafgpu.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "runtime.cpp", "drive.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "runtime.cpp", "drive.cpp",
+                                                  "offload.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("caf_internal.h", "tiles.h")] + [
     os.path.join(ROOT, "include", "caf_gpu.h")]
 ARCH = os.environ.get("CAFGPU_ARCH", "gfx950")

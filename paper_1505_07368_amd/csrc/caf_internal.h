@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/caf_gpu.h"
 
 namespace cafgpu {
@@ -198,6 +200,13 @@ struct DriveQ {
   alignas(64) uint64_t head = 0;  // consumer
   alignas(64) uint64_t tail = 0;  // producer
 };
+
+// The CPU actors of the CPU+GPU split (offload.cpp): a worker pool owned by
+// the system, created on first use and destroyed at shutdown.
+struct CpuPool;
+void cpu_pool_destroy(CpuPool* p);
+CpuPool*& cpu_pool_of(caf_gpu_system* s);
+std::mutex& offload_mu_of(caf_gpu_system* s);  // one split at a time per system
 
 }  // namespace cafgpu
 

@@ -267,8 +267,16 @@ struct caf_gpu_system {
   uint32_t grid_full = 0, grid_light = 0;  // drain-kernel workgroups per variant
   std::atomic<bool> need_full{false};       // a GEMM actor exists
   std::map<PlainShape, PlainGraph> graphs;  // CAF_MODE_PLAIN_GRAPH, guarded by mu
+  // CPU actors of the CPU+GPU split (offload.cpp)
+  cafgpu::CpuPool* cpu_pool = nullptr;
+  std::mutex offload_mu;
   bool plain() const { return cfg.mode == CAF_MODE_PLAIN || cfg.mode == CAF_MODE_PLAIN_GRAPH; }
 };
+
+namespace cafgpu {
+CpuPool*& cpu_pool_of(caf_gpu_system* s) { return s->cpu_pool; }
+std::mutex& offload_mu_of(caf_gpu_system* s) { return s->offload_mu; }
+}  // namespace cafgpu
 
 namespace {
 
@@ -1202,6 +1210,12 @@ double caf_gpu_drain_kernel_ms(caf_gpu_system* s, uint64_t* launches) {
 
 int caf_gpu_shutdown(caf_gpu_system* s) {
   if (!s) return CAF_E_INVALID;
+  {
+    // a CPU+GPU split in progress finishes first; then its workers go
+    std::lock_guard<std::mutex> g(s->offload_mu);
+    cafgpu::cpu_pool_destroy(s->cpu_pool);
+    s->cpu_pool = nullptr;
+  }
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->shut = true;
