@@ -294,6 +294,41 @@ def pipeline_leg(cg, torch, chains=100000, n=128, window=1024, seed=0):
     return out
 
 
+def offload_leg(cg, torch, reps=3, threads=None):
+    """The Sec. 7.5 experiment: the paper's 1920x1080 image of
+    [-0.5-0.7375i, 0.1-0.1375i] in float at max_iter 1200 and 120, with the
+    GPU actor's share of the rows going from 0 to 100% in steps of 10% and
+    the rest on the CPU actors (host worker threads).  Median wall time per
+    image of `reps` runs, and when each share was complete.  The whole image
+    ends in host memory either way (the GPU share is copied back)."""
+    from paper_1505_07368_amd import gen
+    threads = threads or min(16, os.cpu_count() or 1)
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=256)
+    try:
+        a = s.spawn(cg.BHV_MANDELBROT)
+        out = {"cpu_threads": threads, "image": "1920x1080 [-0.5-0.7375i, 0.1-0.1375i], fp32"}
+        for mi in (1200, 120):
+            vp = gen.paper_replica_viewport(mi)
+            image = cg.caf_mandel_args(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width,
+                                       vp.height, 0, vp.height, mi, cg.F32)
+            stage = torch.empty(vp.height * vp.width, dtype=torch.uint16, device="cuda")
+            host = np.zeros((vp.height, vp.width), np.uint16)
+            s.offload_mandel(a, image, vp.height, threads, stage, host)  # warm-up
+            iters = int(host.astype(np.int64).sum())
+            rows = []
+            for k in range(11):
+                g = round(vp.height * k / 10)
+                ts = [s.offload_mandel(a, image, g, threads, stage, host)[1] for _ in range(reps)]
+                med = lambda key: sorted(t[key] for t in ts)[reps // 2] / 1e6
+                rows.append({"gpu_share": k / 10, "gpu_rows": g, "ms": med("total_ns"),
+                             "gpu_done_ms": med("gpu_done_ns"), "cpu_done_ms": med("cpu_done_ns")})
+                log(f"[bench] offload max_iter {mi}: GPU share {k * 10}% -> {rows[-1]['ms']:.2f} ms")
+            out[f"max_iter_{mi}"] = {"iters_per_image": iters, "by_share": rows}
+        return out
+    finally:
+        s.shutdown()
+
+
 def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 << 30):
     """Open-loop Poisson arrivals: 70 % Mandelbrot squares (64^2..512^2,
     max_iter 256..4096, boundary viewports, fp32), 30 % fp32 GEMM with n in
@@ -399,7 +434,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline leg only")
-    ap.add_argument("--legs", default="fp64,forms,small,gemm,pipeline,serving",
+    ap.add_argument("--legs", default="fp64,forms,small,gemm,pipeline,serving,offload",
                     help="comma list of the legs to run beside the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
@@ -517,6 +552,8 @@ def main():
             log(f"[bench] serving {rate:g}/s for {dur:g} s")
             serving[f"{rate:g}"] = serving_leg(cg, torch, rate, duration_s=dur)
         result["serving"] = serving
+    if "offload" in legs:
+        result["offload"] = offload_leg(cg, torch)
     result["tuned"] = tuned
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
