@@ -61,7 +61,8 @@ typedef enum {
   CAF_F32 = 2,
   CAF_F64 = 3,
   CAF_BF16 = 4, /* bfloat16 bit patterns, uint16 storage */
-  CAF_U64 = 5
+  CAF_U64 = 5,
+  CAF_U32 = 6   /* colour-mapped Mandelbrot replies: one uint32 per pixel */
 } caf_dtype;
 
 /* Behaviours a compute actor can be bound to. */
@@ -165,6 +166,16 @@ typedef struct {
   uint32_t n;           /* GEMM n, or tanh/rowsum rows (= cols); 0 = any size */
   uint32_t reserved;
   caf_actor forward_to; /* 0 = reply to the requester; else every reply becomes a request to it */
+  /* Mandelbrot only: a data transformation fused into the handler (the
+   * post-processing step spawn_cl accepts beside the kernel, Sec. 4.6).
+   * With palette_len > 0 every reply is a colour image, CAF_U32
+   * [rows][width], pixel = palette[min(count, palette_len - 1)]: the count
+   * itself is never returned.  palette: device memory, palette_len
+   * (1 .. 65536) entries, caller-owned, unchanged while the actor may still
+   * handle a message.  Both 0: replies are the uint16 counts. */
+  const uint32_t* palette;
+  uint32_t palette_len;
+  uint32_t reserved2;
 } caf_spawn_args;
 
 /* Creates a system on cfg->device.  The arena must stay allocated until
@@ -174,7 +185,9 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out);
 
 /* spawn_cl analog (Sec. 4.6): creates an actor bound to behavior; args may
  * be NULL.  The actor starts waiting for messages.  CAF_E_INVALID for an
- * unknown behaviour or forward target, CAF_E_OVERLOAD past 1024 actors. */
+ * unknown behaviour or forward target, or a palette that is not a
+ * Mandelbrot actor's or not 1 .. 65536 entries at a non-NULL address;
+ * CAF_E_OVERLOAD past 1024 actors. */
 int caf_gpu_spawn(caf_gpu_system* sys, int32_t behavior, const caf_spawn_args* args,
                   caf_actor* out);
 

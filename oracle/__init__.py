@@ -125,6 +125,15 @@ def mandelbrot(re_min, im_min, step_re, step_im, width, row0, rows, max_iter, fp
     return out
 
 
+def colour_map(counts: np.ndarray, palette: np.ndarray) -> np.ndarray:
+    """A Mandelbrot reply after the spawn-time post-processing step (the
+    transformation spawn_cl accepts beside the kernel, Sec. 4.6): each count
+    n becomes palette[min(n, len(palette) - 1)], uint32."""
+    palette = np.asarray(palette, dtype=np.uint32)
+    idx = np.minimum(np.asarray(counts, dtype=np.int64), len(palette) - 1)
+    return palette[idx]
+
+
 def escape(c: complex, max_iter: int, fp="f32") -> int:
     """Count of a single point c (a 1x1 request whose corner is c)."""
     return int(mandelbrot(c.real, c.imag, 0.0, 0.0, 1, 0, 1, max_iter, fp)[0, 0])

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcafgpu.so")
 
 OK, E_INVALID, E_NO_ACTOR, E_OVERLOAD, E_TIMEOUT, E_DEVICE, E_QUIT, E_FAULT = (
     0, -1, -2, -3, -4, -5, -6, -7)
-I32, U16, F32, F64, BF16, U64 = 0, 1, 2, 3, 4, 5
+I32, U16, F32, F64, BF16, U64, U32 = 0, 1, 2, 3, 4, 5, 6
 BHV_NOOP, BHV_MANDELBROT, BHV_GEMM, BHV_TANH, BHV_ROWSUM, BHV_HASHCHAIN, BHV_FAULT = range(7)
 MODE_PLAIN, MODE_BATCHED, MODE_PERSISTENT, MODE_PLAIN_GRAPH = 0, 1, 2, 3
 GROUP_FIFO, GROUP_LPT = 0, 1
@@ -71,7 +71,8 @@ class caf_hash_args(C.Structure):
 
 
 class caf_spawn_args(C.Structure):
-    _fields_ = [("n", C.c_uint32), ("reserved", C.c_uint32), ("forward_to", C.c_uint64)]
+    _fields_ = [("n", C.c_uint32), ("reserved", C.c_uint32), ("forward_to", C.c_uint64),
+                ("palette", C.c_void_p), ("palette_len", C.c_uint32), ("reserved2", C.c_uint32)]
 
 
 class caf_gpu_stats(C.Structure):
@@ -158,7 +159,7 @@ def _torch():
 def dtype_code(t) -> int:
     torch = _torch()
     m = {torch.int32: I32, torch.uint16: U16, torch.float32: F32, torch.float64: F64,
-         torch.bfloat16: BF16, torch.uint64: U64}
+         torch.bfloat16: BF16, torch.uint64: U64, torch.uint32: U32}
     return m[t.dtype]
 
 
@@ -167,14 +168,14 @@ def buf_of(x, dtype: int | None = None) -> caf_buf:
     if isinstance(x, np.ndarray):
         assert x.flags.c_contiguous
         np_map = {np.dtype(np.int32): I32, np.dtype(np.uint16): U16, np.dtype(np.float32): F32,
-                  np.dtype(np.float64): F64, np.dtype(np.uint64): U64}
+                  np.dtype(np.float64): F64, np.dtype(np.uint64): U64, np.dtype(np.uint32): U32}
         return caf_buf(x.ctypes.data, x.size, dtype if dtype is not None else np_map[x.dtype], 0)
     assert x.is_contiguous()
     return caf_buf(x.data_ptr(), x.numel(), dtype if dtype is not None else dtype_code(x),
                    1 if x.is_cuda else 0)
 
 
-_ELEM = {I32: 4, U16: 2, F32: 4, F64: 8, BF16: 2, U64: 8}
+_ELEM = {I32: 4, U16: 2, F32: 4, F64: 8, BF16: 2, U64: 8, U32: 4}
 
 
 class Future:
@@ -237,6 +238,7 @@ class System:
         self.L = load()
         self.device = device
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self._palettes = []  # colour tables of spawned actors, kept alive
         self.stream = torch.cuda.Stream(device=device)
         self.dstream = torch.cuda.Stream(device=device)
         self.mode = MODES[mode] if isinstance(mode, str) else mode
@@ -254,12 +256,21 @@ class System:
         self.h = h
 
     # -- actors ----------------------------------------------------------
-    def spawn(self, behavior: int, n: int = 0, forward_to: int = 0) -> int:
+    def spawn(self, behavior: int, n: int = 0, forward_to: int = 0, palette=None) -> int:
+        """palette (Mandelbrot only): a device tensor of 32-bit colours; the
+        actor then replies with palette[min(count, len - 1)] per pixel.  The
+        system keeps a reference to it."""
         a = C.c_uint64()
         sa = caf_spawn_args(n, 0, forward_to)
+        if palette is not None:
+            assert palette.is_cuda and palette.element_size() == 4 and palette.is_contiguous()
+            sa.palette = palette.data_ptr()
+            sa.palette_len = palette.numel()
         rc = self.L.caf_gpu_spawn(self.h, behavior, C.byref(sa), C.byref(a))
         if rc != OK:
             raise CafError("caf_gpu_spawn", rc)
+        if palette is not None:
+            self._palettes.append(palette)
         return a.value
 
     def quit(self, actor: int, reason: int = 0) -> int:
@@ -350,13 +361,13 @@ class System:
             nb = res.numel * _ELEM[res.dtype]
             raw = (C.c_uint8 * nb).from_address(res.data)
             npd = {I32: np.int32, U16: np.uint16, F32: np.float32, F64: np.float64,
-                   U64: np.uint64}[res.dtype]
+                   U64: np.uint64, U32: np.uint32}[res.dtype]
             return np.frombuffer(bytes(raw), dtype=npd).copy()
         off = res.data - self.arena.data_ptr()
         nb = res.numel * _ELEM[res.dtype]
         if 0 <= off and off + nb <= self.arena.numel():
             tdt = {I32: torch.int32, U16: torch.uint16, F32: torch.float32,
-                   F64: torch.float64, U64: torch.uint64}[res.dtype]
+                   F64: torch.float64, U64: torch.uint64, U32: torch.uint32}[res.dtype]
             return self.arena[off:off + nb].view(tdt)
         return None  # written into a caller-owned out tensor
 

@@ -36,7 +36,9 @@ enum DescFlags : uint16_t {
   DF_INLINE_IN = 4,  // echo input travels in the parameter block
   DF_INLINE_OUT = 8, // reply (<= 16 B) travels in the completion record
   DF_SEND = 16,      // no reply wanted; the completion only recycles the slot
-  DF_NO_COMPLETE = 32 // plain mode, non-final pipeline stage: no completion record
+  DF_NO_COMPLETE = 32, // plain mode, non-final pipeline stage: no completion record
+  DF_RGBA = 64        // Mandelbrot colour reply: uint32 palette[min(count, numel - 1)],
+                      // palette at in0, its length in numel
 };
 
 // One message: a 128-byte mailbox entry.

@@ -173,6 +173,7 @@ size_t dtype_bytes(int32_t dt) {
     case CAF_F64: return 8;
     case CAF_BF16: return 2;
     case CAF_U64: return 8;
+    case CAF_U32: return 4;
   }
   return 0;
 }
@@ -541,7 +542,8 @@ int check_signature(const ActorRec& a, const void* args, uint64_t args_bytes, co
       if (m->fp != CAF_F32 && m->fp != CAF_F64) return CAF_E_INVALID;
       if ((uint64_t)m->row0 + m->rows > m->height) return CAF_E_INVALID;
       if (m->width > (1u << 20) || m->rows > (1u << 20)) return CAF_E_INVALID;
-      *out = Shape{CAF_U16, (uint64_t)m->rows * m->width, m->rows, m->width};
+      *out = Shape{a.spawn.palette_len ? CAF_U32 : CAF_U16, (uint64_t)m->rows * m->width, m->rows,
+                   m->width};
       return CAF_OK;
     }
     case CAF_BHV_GEMM: {
@@ -612,6 +614,11 @@ void fill_desc(const caf_gpu_system* s, const ActorRec& a, uint32_t aidx, const 
       d->p.m64.rows = m->rows;
       d->p.m64.max_iter = m->max_iter;
       d->tcfg = s->mandel_tile_px;
+      if (a.spawn.palette_len) {
+        d->flags |= DF_RGBA;
+        d->in0 = (uint64_t)(uintptr_t)a.spawn.palette;
+        d->numel = a.spawn.palette_len;
+      }
       break;
     }
     case CAF_BHV_GEMM: {
@@ -840,7 +847,7 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
       return CAF_E_NO_ACTOR;
     }
   }
-  d.in0 = inptr[0];
+  if (n_in) d.in0 = inptr[0];  // else fill_desc's (a colour palette, or 0)
   d.in1 = inptr[1];
   d.out = stage_out[0];
   for (uint32_t h = 0; h < nhops; ++h) d.hop_out[h] = stage_out[h + 1];
@@ -1082,6 +1089,11 @@ int caf_gpu_spawn(caf_gpu_system* s, int32_t behavior, const caf_spawn_args* arg
   ActorRec a;
   a.behavior = behavior;
   if (args) a.spawn = *args;
+  if (a.spawn.palette_len || a.spawn.palette) {
+    if (behavior != CAF_BHV_MANDELBROT || !a.spawn.palette || a.spawn.palette_len == 0 ||
+        a.spawn.palette_len > 65536)
+      return CAF_E_INVALID;
+  }
   if (a.spawn.forward_to &&
       (a.spawn.forward_to > s->actors.size() || !s->actors[a.spawn.forward_to - 1].alive))
     return CAF_E_INVALID;

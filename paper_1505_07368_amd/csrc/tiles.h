@@ -129,6 +129,11 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
   const uint32_t width = d.p.m64.width, row0 = d.p.m64.row0, rows = d.p.m64.rows;
   const uint32_t max_iter = d.p.m64.max_iter;
   uint16_t* out = reinterpret_cast<uint16_t*>(d.out);
+  // colour reply (a transformation fused at spawn): palette[min(n, len - 1)]
+  const bool rgba = (d.flags & DF_RGBA) != 0;
+  const auto pal = global_ptr(reinterpret_cast<const uint32_t*>(d.in0));
+  const uint32_t pal_last = d.numel - 1u;
+  const auto out32 = global_ptr(reinterpret_cast<uint32_t*>(d.out));
   const uint32_t bw = (width + kMandelBlockW - 1) / kMandelBlockW;
   const uint32_t nb = mandel_blocks(width, rows);
   const uint32_t bpt = d.tcfg / 64;
@@ -163,8 +168,12 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
     uint32_t n[2];
     escape_count2<T>(cr[0], ci[0], cr[1], ci[1], max_iter, v[0], v[1], n[0], n[1]);
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
-      if (v[k]) out[(uint64_t)y[k] * width + x[k]] = (uint16_t)n[k];
+    for (int k = 0; k < 2; ++k) {
+      if (!v[k]) continue;
+      const uint64_t at = (uint64_t)y[k] * width + x[k];
+      if (rgba) out32[at] = pal[min(n[k], pal_last)];
+      else out[at] = (uint16_t)n[k];
+    }
   }
 }
 

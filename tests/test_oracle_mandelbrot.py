@@ -176,3 +176,16 @@ def test_precisions_differ_near_cusp():
     a = o.escape(complex(0.25 + 1e-6, 0), 100000, "f32")
     b = o.escape(complex(0.25 + 1e-6, 0), 100000, "f64")
     assert a != b
+
+
+def test_colour_map_is_a_clamped_lookup():
+    """The spawn-time colour transformation: a count indexes the palette and
+    counts past its end take the last entry (hand orbits: c = 1 escapes at
+    3, c = 1/2 at 5, c = -2.5 at 1, c = 0 never)."""
+    pal = np.array([0x11, 0x22, 0x33, 0x44, 0x55], np.uint32)
+    counts = np.array([[o.escape(1 + 0j, 1000), o.escape(0.5 + 0j, 1000), o.escape(0j, 1000),
+                        o.escape(-2.5 + 0j, 1000)]], np.uint16)
+    got = o.colour_map(counts, pal)
+    assert got.dtype == np.uint32
+    assert got.tolist() == [[0x44, 0x55, 0x55, 0x22]]
+    assert o.colour_map(counts, pal[:1]).tolist() == [[0x11] * 4]
