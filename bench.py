@@ -74,8 +74,12 @@ def percentiles(lat_ns):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
-def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tune=None):
-    """Runs the image workload in one delivery mode; returns a dict.
+def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tune=None,
+               palette=None):
+    """Runs the image workload in one delivery mode; returns a dict.  With a
+    palette (device int32 tensor) the timed steps go to an actor spawned with
+    it, so every reply is a colour image; the work per step is still the sum
+    of the escape counts, taken from a counts run of the same messages.
 
     The timed steps are bracketed by device synchronisation, except for the
     persistent form: its drain kernel stays resident for a long idle linger
@@ -101,7 +105,8 @@ def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tu
         # the timed steps issue a prebuilt message array (the caller's
         # marshalling is not part of a step)
         from paper_1505_07368_amd import autotune, gen
-        arr, arr_args = autotune.mandel_messages(a, [gen.boundary_viewport(sd) for sd in seeds],
+        timed = a if palette is None else s.spawn(cg.BHV_MANDELBROT, palette=palette)
+        arr, arr_args = autotune.mandel_messages(timed, [gen.boundary_viewport(sd) for sd in seeds],
                                                  fp=fp)
         assert len(arr) == len(msgs)
         for _ in range(warmup):
@@ -434,7 +439,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="headline leg only")
-    ap.add_argument("--legs", default="fp64,forms,small,gemm,pipeline,serving,offload",
+    ap.add_argument("--legs", default="fp64,colour,forms,small,gemm,pipeline,serving,offload",
                     help="comma list of the legs to run beside the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="library defaults, no autotuning")
@@ -511,6 +516,18 @@ def main():
             result["fp64"]["alu_frac"] = round(
                 f64["iters_per_step"] * max(2, args.steps // 2) * OPS_PER_ITER
                 / (f64["kernel_ms_total"] * 1e-3) / VALU_LANE_OPS, 4)
+    if "colour" in legs:
+        # the same batch through an actor spawned with a 256-entry palette:
+        # the colour map is fused into the tile's store (4-byte pixels)
+        log("[bench] batched fp32, colour replies")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(3)
+        pal = torch.randint(-2 ** 31, 2 ** 31 - 1, (256,), generator=g, device="cuda",
+                            dtype=torch.int32)
+        col = mandel_leg(cg, torch, "batched", cg.F32, args.steps, args.warmup, seeds, True,
+                         tune=tuned.get("mandel"), palette=pal)
+        result["colour"] = {k: col[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
+        result["colour"]["vs_counts"] = round(col["giter_s"] / result["value"], 4)
     if "forms" in legs:
         for mode in ("persistent", "plain", "plain_graph"):
             log(f"[bench] {mode} fp32")
