@@ -235,6 +235,17 @@ void caf_future_release(caf_future* fut);
  * completes normally. */
 int caf_gpu_quit(caf_gpu_system* sys, caf_actor actor, uint32_t exit_reason);
 
+/* become (Sec. 6): the actor's behaviour, signature and spawn arguments
+ * change for every message submitted after this call; messages submitted
+ * before it are still handled by the old behaviour (each carries its
+ * behaviour through the mailbox), so the swap takes effect in mailbox order.
+ * The actor's device-resident state and the order in which its stateful
+ * messages update it carry over.  CAF_E_NO_ACTOR for an unknown or quit
+ * actor; CAF_E_INVALID for an unknown behaviour, forward target or palette
+ * (as for caf_gpu_spawn). */
+int caf_gpu_become(caf_gpu_system* sys, caf_actor actor, int32_t behavior,
+                   const caf_spawn_args* args);
+
 /* Blocks until every accepted message is handled (all replies delivered). */
 int caf_gpu_drain(caf_gpu_system* sys, int64_t timeout_ns);
 

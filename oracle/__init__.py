@@ -105,6 +105,7 @@ def lib():
         L.caf_ref_dequeue_log.restype = u64
         L.caf_ref_actor_state.argtypes = [vp, u64]
         L.caf_ref_actor_state.restype = u64
+        L.caf_ref_become.argtypes = [vp, u64, i32, C.POINTER(SpawnArgs)]
         _lib = L
     return _lib
 
@@ -233,6 +234,10 @@ class System:
 
     def quit(self, actor, reason=0) -> int:
         return self.L.caf_ref_quit(self.h, actor, reason)
+
+    def become(self, actor, behavior: int, n: int = 0, forward_to: int = 0) -> int:
+        sa = SpawnArgs(n, forward_to)
+        return self.L.caf_ref_become(self.h, actor, behavior, C.byref(sa))
 
     def timeout(self, req) -> int:
         return self.L.caf_ref_timeout(self.h, req)

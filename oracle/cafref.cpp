@@ -156,11 +156,16 @@ struct Msg {
   std::vector<int32_t> in_dtype;
   std::vector<uint64_t> in_numel;
   uint64_t forward_to;
+  bool become = false;  // a control entry: switch the behaviour when dequeued
+  int32_t become_behavior = 0;
+  ref_spawn_args become_spawn{0, 0};
 };
 
 struct Actor {
-  int32_t behavior;
+  int32_t behavior;  // the behaviour the next dequeued message meets
   ref_spawn_args spawn;
+  int32_t tail_behavior;  // ... and the one a message enqueued now will meet
+  ref_spawn_args tail_spawn;
   bool alive;
   uint64_t state;  // hash-chain state
   std::deque<Msg> mailbox;
@@ -216,9 +221,9 @@ static void resolve(ref_system* s, uint64_t req, int32_t status, int32_t dtype,
 // Checks a message against the actor's signature (Sec. 4.5 typed
 // interfaces, Sec. 4.6 element counts fixed at spawn).  Returns REF_OK or
 // REF_E_INVALID.
-static int check_signature(const Actor& a, const void* args, uint64_t args_bytes,
-                           const ref_buf* in, uint32_t n_in) {
-  switch (a.behavior) {
+static int check_signature(int32_t behavior, const ref_spawn_args& spawn, const void* args,
+                           uint64_t args_bytes, const ref_buf* in, uint32_t n_in) {
+  switch (behavior) {
     case REF_BHV_NOOP:
       if (n_in != 1 || in[0].dtype != REF_I32 || in[0].numel == 0) return REF_E_INVALID;
       return REF_OK;
@@ -234,7 +239,7 @@ static int check_signature(const Actor& a, const void* args, uint64_t args_bytes
       if (args_bytes != sizeof(ref_gemm_args) || n_in != 2) return REF_E_INVALID;
       const ref_gemm_args* g = (const ref_gemm_args*)args;
       if (g->n == 0 || (g->in_dtype != REF_F32 && g->in_dtype != REF_BF16)) return REF_E_INVALID;
-      if (a.spawn.n != 0 && a.spawn.n != g->n) return REF_E_INVALID;
+      if (spawn.n != 0 && spawn.n != g->n) return REF_E_INVALID;
       uint64_t nn = (uint64_t)g->n * g->n;
       for (uint32_t i = 0; i < 2; ++i)
         if (in[i].dtype != g->in_dtype || in[i].numel != nn) return REF_E_INVALID;
@@ -245,7 +250,7 @@ static int check_signature(const Actor& a, const void* args, uint64_t args_bytes
       if (args_bytes != sizeof(ref_shape_args) || n_in != 1) return REF_E_INVALID;
       const ref_shape_args* sh = (const ref_shape_args*)args;
       if (sh->rows == 0 || sh->cols == 0) return REF_E_INVALID;
-      if (a.spawn.n != 0 && (a.spawn.n != sh->rows || a.spawn.n != sh->cols)) return REF_E_INVALID;
+      if (spawn.n != 0 && (spawn.n != sh->rows || spawn.n != sh->cols)) return REF_E_INVALID;
       if (in[0].dtype != REF_F32 && in[0].dtype != REF_F64) return REF_E_INVALID;
       if (in[0].numel != (uint64_t)sh->rows * sh->cols) return REF_E_INVALID;
       return REF_OK;
@@ -269,6 +274,8 @@ extern "C" int caf_ref_spawn(ref_system* sys, int32_t behavior, const ref_spawn_
   Actor a;
   a.behavior = behavior;
   a.spawn = args ? *args : ref_spawn_args{0, 0};
+  a.tail_behavior = a.behavior;
+  a.tail_spawn = a.spawn;
   a.alive = true;
   a.state = 0;
   sys->actors.push_back(std::move(a));
@@ -281,7 +288,7 @@ static int enqueue(ref_system* sys, uint64_t actor, uint32_t sender, const void*
                    uint64_t req) {
   Actor* a = find_actor(sys, actor);
   if (a == nullptr || !a->alive) return REF_E_NO_ACTOR;
-  int st = check_signature(*a, args, args_bytes, in, n_in);
+  int st = check_signature(a->tail_behavior, a->tail_spawn, args, args_bytes, in, n_in);
   if (st != REF_OK) return st;
   if (forward_to != 0) {
     Actor* f = find_actor(sys, forward_to);
@@ -343,6 +350,11 @@ static std::vector<uint8_t> as_bytes(const std::vector<V>& v) {
 // forwards it, Sec. 5 "redistribute tasks" between actors).
 static void handle(ref_system* sys, uint64_t actor_id, Msg& m) {
   Actor& a = sys->actors[actor_id - 1];
+  if (m.become) {
+    a.behavior = m.become_behavior;
+    a.spawn = m.become_spawn;
+    return;
+  }
   a.log.emplace_back(m.sender, m.seq);
   int32_t status = REF_OK;
   int32_t dtype = REF_U16;
@@ -431,7 +443,7 @@ static void handle(ref_system* sys, uint64_t actor_id, Msg& m) {
     }
     ref_shape_args sh{out_rows, out_cols};
     ref_buf b{out.data(), out.size() / dtype_size(dtype), dtype};
-    int st = check_signature(*f, &sh, sizeof sh, &b, 1);
+    int st = check_signature(f->tail_behavior, f->tail_spawn, &sh, sizeof sh, &b, 1);
     if (st != REF_OK) {
       resolve(sys, m.req, st, 0, {});
       return;
@@ -449,6 +461,30 @@ static void handle(ref_system* sys, uint64_t actor_id, Msg& m) {
     return;
   }
   resolve(sys, m.req, status, dtype, std::move(out));
+}
+
+extern "C" int caf_ref_become(ref_system* sys, uint64_t actor, int32_t behavior,
+                              const ref_spawn_args* args) {
+  Actor* a = find_actor(sys, actor);
+  if (a == nullptr || !a->alive) return REF_E_NO_ACTOR;
+  if (behavior < REF_BHV_NOOP || behavior > REF_BHV_FAULT) return REF_E_INVALID;
+  const ref_spawn_args sp = args ? *args : ref_spawn_args{0, 0};
+  if (sp.forward_to != 0) {
+    Actor* f = find_actor(sys, sp.forward_to);
+    if (f == nullptr || !f->alive) return REF_E_INVALID;
+  }
+  Msg m;
+  m.req = 0;
+  m.sender = 0;
+  m.seq = 0;
+  m.forward_to = 0;
+  m.become = true;
+  m.become_behavior = behavior;
+  m.become_spawn = sp;
+  a->mailbox.push_back(std::move(m));
+  a->tail_behavior = behavior;
+  a->tail_spawn = sp;
+  return REF_OK;
 }
 
 extern "C" uint64_t caf_ref_run(ref_system* sys) {

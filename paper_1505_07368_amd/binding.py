@@ -29,7 +29,7 @@ EXPORTED = ["caf_gpu_init", "caf_gpu_spawn", "caf_gpu_send", "caf_gpu_request",
             "caf_future_wait", "caf_future_poll", "caf_future_id", "caf_future_release",
             "caf_gpu_quit", "caf_gpu_drain", "caf_gpu_shutdown", "caf_gpu_strerror",
             "caf_gpu_get_stats", "caf_gpu_drain_kernel_ms", "caf_gpu_drive",
-            "caf_cpu_mandel_rows", "caf_offload_mandel"]
+            "caf_cpu_mandel_rows", "caf_offload_mandel", "caf_gpu_become"]
 
 
 class caf_buf(C.Structure):
@@ -120,6 +120,7 @@ def load():
         "caf_gpu_drive": ([vp, P(caf_msg), u64, u32, vp, u32, vp, vp, vp, P(C.c_double)],
                           C.c_int),
         "caf_cpu_mandel_rows": ([P(caf_mandel_args), u32, u32, vp], C.c_int),
+        "caf_gpu_become": ([vp, u64, i32, P(caf_spawn_args)], C.c_int),
         "caf_offload_mandel": ([vp, u64, P(caf_mandel_args), u32, u32, vp, vp,
                                 P(caf_offload_times)], C.c_int),
     }
@@ -275,6 +276,17 @@ class System:
 
     def quit(self, actor: int, reason: int = 0) -> int:
         return self.L.caf_gpu_quit(self.h, actor, reason)
+
+    def become(self, actor: int, behavior: int, n: int = 0, forward_to: int = 0,
+               palette=None) -> int:
+        """caf_gpu_become: later messages meet the new behaviour."""
+        sa = caf_spawn_args(n, 0, forward_to)
+        if palette is not None:
+            assert palette.is_cuda and palette.element_size() == 4 and palette.is_contiguous()
+            sa.palette = palette.data_ptr()
+            sa.palette_len = palette.numel()
+            self._palettes.append(palette)
+        return self.L.caf_gpu_become(self.h, actor, behavior, C.byref(sa))
 
     @staticmethod
     def _bufs(inputs):

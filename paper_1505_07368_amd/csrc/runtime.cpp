@@ -872,7 +872,9 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   const uint64_t rid = (s->req_seq++ << kSlotBits) | slot;
   d.req_id = rid;
   d.slot = slot;
-  d.seq = s->actors[aidx].seq++;
+  // Only stateful messages take a number: the device applies them to the
+  // actor's state strictly in this order (other behaviours never wait on it).
+  if (a.behavior == CAF_BHV_HASHCHAIN) d.seq = s->actors[aidx].seq++;
   SlotInfo& si = s->slots[slot];
   si.req_id = rid;
   si.fut = f;
@@ -906,7 +908,7 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
         sd.p.s.cols = ps.cols;
         sd.flags = (uint16_t)(d.flags & DF_SEND);
         sd.tcfg = 0;
-        sd.seq = s->actors[hidx[k - 1]].seq++;
+        sd.seq = 0;  // pipeline stages keep no state
       }
       sd.hop_actor[0] = sd.hop_actor[1] = 0;
       if (k < nhops) sd.flags |= DF_NO_COMPLETE;
@@ -1103,6 +1105,32 @@ int caf_gpu_spawn(caf_gpu_system* s, int32_t behavior, const caf_spawn_args* arg
   s->actors.push_back(a);
   __atomic_fetch_or(&s->hctl->alive[idx >> 5], 1u << (idx & 31), __ATOMIC_SEQ_CST);
   *out = idx + 1;
+  return CAF_OK;
+}
+
+int caf_gpu_become(caf_gpu_system* s, caf_actor actor, int32_t behavior,
+                   const caf_spawn_args* args) {
+  if (!s) return CAF_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->shut) return CAF_E_INVALID;
+  if (actor == 0 || actor > s->actors.size() || !s->actors[actor - 1].alive)
+    return CAF_E_NO_ACTOR;
+  if (behavior < CAF_BHV_NOOP || behavior > CAF_BHV_FAULT) return CAF_E_INVALID;
+  caf_spawn_args sp{};
+  if (args) sp = *args;
+  if ((sp.palette_len || sp.palette) &&
+      (behavior != CAF_BHV_MANDELBROT || !sp.palette || sp.palette_len == 0 ||
+       sp.palette_len > 65536))
+    return CAF_E_INVALID;
+  if (sp.forward_to && (sp.forward_to > s->actors.size() || !s->actors[sp.forward_to - 1].alive))
+    return CAF_E_INVALID;
+  // Every later request is checked against, and carries, the new behaviour;
+  // those already submitted carry the old one.  The device state and the
+  // stateful sequence continue.
+  ActorRec& a = s->actors[actor - 1];
+  a.behavior = behavior;
+  a.spawn = sp;
+  if (behavior == CAF_BHV_GEMM) s->need_full.store(true);
   return CAF_OK;
 }
 

@@ -177,6 +177,75 @@ def test_nonblocking_admission_overload():
         assert f4.wait(30)[0] == cg.OK
 
 
+def test_become_matches_oracle_sequence(sysm):
+    """become (Sec. 6) through the mailbox: hash-chain, echo and Mandelbrot
+    messages with swaps in between, all submitted before any reply is read;
+    every reply and the final state equal the oracle's run of the same
+    sequence, and the state survives swaps away and back."""
+    from paper_1505_07368_amd import binding as cg
+    vp = gen.tiny_viewport()
+    margs = cg.caf_mandel_args(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width,
+                               vp.height, 40, 9, vp.max_iter, cg.F32)
+    x = np.array([7, -8, 9], np.int32)
+    a = sysm.spawn(cg.BHV_HASHCHAIN)
+    ref = oracle.System()
+    ra = ref.spawn(oracle.BHV_HASHCHAIN)
+    futs, rreqs = [], []
+
+    def hash_(v):
+        futs.append(sysm.request(a, cg.caf_hash_args(v)))
+        rreqs.append(ref.request(ra, 0, args=np.uint64(v).tobytes())[1])
+
+    def swap(beh, rbeh):
+        assert sysm.become(a, beh) == cg.OK
+        assert ref.become(ra, rbeh) == oracle.OK
+
+    hash_(11)
+    hash_(22)
+    swap(cg.BHV_NOOP, oracle.BHV_NOOP)
+    rc, f = sysm.request_raw(a, cg.caf_hash_args(5))  # checked against the new behaviour
+    assert rc == cg.E_INVALID and f is None
+    futs.append(sysm.request(a, inputs=[x]))
+    rreqs.append(ref.request(ra, 0, inputs=[(x, oracle.I32)])[1])
+    swap(cg.BHV_HASHCHAIN, oracle.BHV_HASHCHAIN)
+    hash_(33)
+    swap(cg.BHV_MANDELBROT, oracle.BHV_MANDELBROT)
+    futs.append(sysm.request(a, margs))
+    rreqs.append(ref.request(ra, 0, args=oracle.mandel_args(
+        vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, vp.height, 40, 9,
+        vp.max_iter))[1])
+    swap(cg.BHV_HASHCHAIN, oracle.BHV_HASHCHAIN)
+    hash_(44)
+    ref.run()
+    for f, r in zip(futs, rreqs):
+        st, v = f.result()
+        ok, rst, data, _ = ref.reply(r)
+        assert ok and st == rst == cg.OK
+        got = v.cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)
+        assert np.array_equal(got.ravel(), data.ravel())
+    assert sysm.become(a, 99) == cg.E_INVALID
+    assert sysm.quit(a) == cg.OK
+    assert sysm.become(a, cg.BHV_NOOP) == cg.E_NO_ACTOR
+
+
+def test_become_gemm_while_a_light_launch_runs():
+    """An echo actor becomes a GEMM actor while the drain kernel without
+    matrix tiles is running: the product is still computed."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode="batched", arena_bytes=64 << 20, ring_slots=64,
+                   idle_exit_us=200000) as s:
+        e = s.spawn(cg.BHV_NOOP)
+        st, v = s.request(e, inputs=[np.array([3], np.int32)]).result()
+        assert st == cg.OK and int(v[0]) == 3
+        assert s.become(e, cg.BHV_GEMM) == cg.OK
+        A, B = gen.gemm_pair(77, 64)
+        At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        st, C = s.request(e, cg.caf_gemm_args(64, cg.F32), inputs=[At, Bt]).result()
+        assert st == cg.OK
+        assert rel_fro(C.cpu().numpy().reshape(64, 64), oracle.gemm(A, B)) <= 1e-5
+
+
 def test_batched_pingpong_keeps_its_launch():
     """Window-1 ping-pong in batched mode (default 50 us linger): the drain
     launch stays up between requests instead of retiring in every gap (a

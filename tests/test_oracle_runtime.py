@@ -170,3 +170,32 @@ def test_interleaving_is_valid_merge():
         for snd in (0, 1):
             qs = [q for sd, q in log if sd == snd]
             assert qs == sorted(qs) == list(range(len(qs)))
+
+
+def test_become_swaps_behaviour_in_mailbox_order_and_keeps_state():
+    """become (Sec. 6): messages enqueued before a swap meet the old
+    behaviour and later ones the new; the actor's state survives a swap away
+    and back; the enqueue-time signature check follows the latest swap."""
+    s = o.System()
+    a = s.spawn(o.BHV_HASHCHAIN)
+    _, r1 = s.request(a, 0, args=u64(11))
+    _, r2 = s.request(a, 0, args=u64(22))
+    assert s.become(a, o.BHV_NOOP) == o.OK
+    assert s.request(a, 0, args=u64(5))[0] == o.E_INVALID  # before anything ran
+    x = np.array([7, 8], np.int32)
+    st, r3 = s.request(a, 0, inputs=[(x, o.I32)])
+    assert st == o.OK
+    assert s.become(a, o.BHV_HASHCHAIN) == o.OK
+    _, r4 = s.request(a, 0, args=u64(33))
+    assert s.run() == 6  # four messages and two swaps
+    h1 = o.hash_step(0, 11)
+    h2 = o.hash_step(h1, 22)
+    h3 = o.hash_step(h2, 33)
+    assert int(s.reply(r1)[2][0]) == h1 and int(s.reply(r2)[2][0]) == h2
+    ok, st, data, _ = s.reply(r3)
+    assert ok and st == o.OK and (data == x).all()
+    assert int(s.reply(r4)[2][0]) == h3 and s.state(a) == h3
+    assert s.dequeue_log(a) == [(0, 0), (0, 1), (0, 2), (0, 3)]  # messages, not swaps
+    assert s.become(a, 99) == o.E_INVALID
+    assert s.quit(a) == o.OK
+    assert s.become(a, o.BHV_NOOP) == o.E_NO_ACTOR
