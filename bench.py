@@ -139,7 +139,9 @@ def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tu
 
 def small_leg(cg, torch, mode, kind, count, window):
     """Small messages through one form: echo (int32), 64x64 Mandelbrot tile,
-    or n = 64 fp32 GEMM.  Returns msgs/s and latency percentiles."""
+    n = 64 fp32 GEMM, or a stateful hash-chain step (device-resident state,
+    updated strictly in mailbox order).  Returns msgs/s and latency
+    percentiles."""
     from paper_1505_07368_amd import gen
     s = cg.System(mode=mode, arena_bytes=256 << 20, ring_slots=4096, idle_exit_us=200000)
     try:
@@ -149,6 +151,9 @@ def small_leg(cg, torch, mode, kind, count, window):
             x = np.array([42], np.int32)
             keep.append(x)
             msgs = [{"actor": a, "inputs": [x]} for _ in range(count)]
+        elif kind == "hash":
+            a = s.spawn(cg.BHV_HASHCHAIN)
+            msgs = [{"actor": a, "args": cg.caf_hash_args(i * 2654435761)} for i in range(count)]
         elif kind == "mandel64":
             a = s.spawn(cg.BHV_MANDELBROT)
             vp = gen.tiny_viewport()
@@ -536,7 +541,8 @@ def main():
             result[mode] = {k: r[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
     if "small" in legs:
         small = {}
-        for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096)):
+        for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096),
+                            ("hash", 4096)):
             for window in ((1, 64, 1024) if kind == "echo" else (256,)):
                 row = {}
                 for mode in ("plain", "plain_graph", "batched", "persistent"):
