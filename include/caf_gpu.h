@@ -324,14 +324,15 @@ int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t count, uint
  * at most 64 rows whose replies are written into dev_stage (device memory,
  * at least gpu_rows * width uint16, caller-owned) and then copied to
  * out_host; at the same time rows [gpu_rows, height) are computed by
- * `cpu_threads` worker threads of the system (0 = one per hardware thread;
- * the pool is created on first use and kept until caf_gpu_shutdown).
+ * `cpu_threads` worker threads of the system (0 = one per hardware thread,
+ * at most 1024; the pool is created on first use and kept until
+ * caf_gpu_shutdown).
  * out_host: uint16 [height][width], caller-owned host memory.  times
  * (optional): wall time of the call, and when each share was complete in
  * host memory, from the start of the call.  Calls on one system run one at
- * a time.  Returns CAF_OK, CAF_E_INVALID for bad arguments, a call-time
- * error of a request, the first error reply, or CAF_E_DEVICE if the copy
- * fails. */
+ * a time.  Returns CAF_OK, CAF_E_INVALID for bad arguments, CAF_E_OVERLOAD
+ * if the worker threads cannot be started, a call-time error of a request,
+ * the first error reply, or CAF_E_DEVICE if the copy fails. */
 typedef struct {
   int64_t total_ns;
   int64_t gpu_done_ns; /* the GPU share in out_host (0 if gpu_rows = 0) */

@@ -74,15 +74,22 @@ namespace cafgpu {
 struct CpuPool {
   static constexpr uint32_t kGrab = 4;  // rows per claim
   explicit CpuPool(uint32_t n) : nthreads(n) {
-    for (uint32_t i = 0; i < n; ++i) th.emplace_back([this] { work(); });
+    try {
+      for (uint32_t i = 0; i < n; ++i) th.emplace_back([this] { work(); });
+    } catch (...) {
+      stop_all();  // the threads already started must be joined before unwinding
+      throw;
+    }
   }
-  ~CpuPool() {
+  ~CpuPool() { stop_all(); }
+  void stop_all() {
     {
       std::lock_guard<std::mutex> g(mu);
       stop = true;
     }
     cv.notify_all();
     for (auto& t : th) t.join();
+    th.clear();
   }
   // Starts rows [r0, r1) of `a` into out (row r0 first); returns at once.
   void post(const caf_mandel_args& a, uint32_t r0, uint32_t r1, uint16_t* out) {
@@ -144,6 +151,8 @@ void cpu_pool_destroy(CpuPool* p) { delete p; }
 
 using cafgpu::CpuPool;
 
+constexpr uint32_t kMaxCpuThreads = 1024;
+
 extern "C" int caf_cpu_mandel_rows(const caf_mandel_args* a, uint32_t row_begin, uint32_t row_end,
                                    uint16_t* out_host) {
   if (!args_ok(a) || !out_host || row_begin > row_end || row_end > a->height)
@@ -159,13 +168,19 @@ extern "C" int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor,
   if (!sys || !args_ok(image) || image->row0 != 0 || image->rows != image->height ||
       gpu_rows > image->height || !out_host || (gpu_rows && !dev_stage))
     return CAF_E_INVALID;
+  if (cpu_threads > kMaxCpuThreads) return CAF_E_INVALID;
   if (cpu_threads == 0) cpu_threads = std::max(1u, std::thread::hardware_concurrency());
   const uint32_t width = image->width, height = image->height;
   std::lock_guard<std::mutex> one_at_a_time(cafgpu::offload_mu_of(sys));
   CpuPool*& pool = cafgpu::cpu_pool_of(sys);
   if (gpu_rows < height && (!pool || pool->nthreads != cpu_threads)) {
     delete pool;
-    pool = new CpuPool(cpu_threads);
+    pool = nullptr;
+    try {
+      pool = new CpuPool(cpu_threads);
+    } catch (...) {  // no exception crosses the C ABI
+      return CAF_E_OVERLOAD;
+    }
   }
   const int64_t t0 = now_ns();
   if (gpu_rows < height) pool->post(*image, gpu_rows, height, out_host + (uint64_t)gpu_rows * width);

@@ -49,6 +49,7 @@ def test_split_refuses_bad_arguments():
         assert L.caf_offload_mandel(s.h, a, good, vp.height + 1, 2, st, o, None) == cg.E_INVALID
         assert L.caf_offload_mandel(s.h, a, good, 8, 2, None, o, None) == cg.E_INVALID
         assert L.caf_offload_mandel(s.h, a, good, 8, 2, st, None, None) == cg.E_INVALID
+        assert L.caf_offload_mandel(s.h, a, good, 8, 1025, st, o, None) == cg.E_INVALID
         tile = cg.caf_mandel_args(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width,
                                   vp.height, 8, 8, 120, cg.F32)  # not the whole image
         assert L.caf_offload_mandel(s.h, a, tile, 8, 2, st, o, None) == cg.E_INVALID
