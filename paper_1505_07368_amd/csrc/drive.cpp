@@ -55,13 +55,19 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
   }
   uint64_t qcap = 64;
   while (qcap < 2ull * window + 64) qcap <<= 1;
-  std::vector<uint32_t> qbuf(qcap);
+  std::vector<uint32_t> qbuf;
+  std::vector<Pending> pend;
+  std::vector<uint32_t> free_tags;
+  try {  // no exception crosses the C ABI; nothing is issued before this
+    qbuf.resize(qcap);
+    pend.resize(window);
+    free_tags.reserve(window);
+  } catch (...) {
+    return CAF_E_OVERLOAD;
+  }
   cafgpu::DriveQ q;
   q.buf = qbuf.data();
   q.mask = qcap - 1;
-  std::vector<Pending> pend(window);
-  std::vector<uint32_t> free_tags;
-  free_tags.reserve(window);
   for (uint32_t k = 0; k < window; ++k) free_tags.push_back(window - 1 - k);
   int first_err = CAF_OK;
   uint64_t next = 0, done = 0;

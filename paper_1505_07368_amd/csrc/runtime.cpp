@@ -941,8 +941,12 @@ int cafgpu_request_tagged(caf_gpu_system* s, caf_actor dst, uint32_t sender, con
                           DriveQ* q, uint32_t tag) {
   if (!fut) return CAF_E_INVALID;
   *fut = nullptr;
-  return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut, true,
-                q, tag);
+  try {
+    return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut,
+                  true, q, tag);
+  } catch (...) {  // thrown before the message is published: nothing is pending
+    return CAF_E_OVERLOAD;
+  }
 }
 
 int64_t cafgpu_future_issue_ns(const caf_future* f) { return f->t_issue; }
@@ -1052,9 +1056,15 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
     delete s;
     return CAF_E_DEVICE;
   }
-  s->actors.reserve(kMaxActors);
-  s->slots.resize(cap);
-  s->free_slots.reserve(cap);
+  try {
+    s->actors.reserve(kMaxActors);
+    s->slots.resize(cap);
+    s->free_slots.reserve(cap);
+    s->pend_slots.reserve(cap);
+  } catch (...) {  // no exception crosses the C ABI
+    caf_gpu_shutdown(s);
+    return CAF_E_DEVICE;
+  }
   for (uint32_t i = 0; i < cap; ++i) s->free_slots.push_back(cap - 1 - i);
   KArgs& a = s->kargs;
   a.hctl = s->hctl;
@@ -1076,7 +1086,12 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   a.grouping = (uint32_t)cfg->grouping;
   a.grid = s->grid_full;
   a.full = 1;
-  s->poller = std::thread(poller_main, s);
+  try {
+    s->poller = std::thread(poller_main, s);
+  } catch (...) {
+    caf_gpu_shutdown(s);
+    return CAF_E_DEVICE;
+  }
   *out = s;
   return CAF_OK;
 }
@@ -1136,8 +1151,12 @@ int caf_gpu_become(caf_gpu_system* s, caf_actor actor, int32_t behavior,
 
 int caf_gpu_send(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
                  uint64_t args_bytes, const caf_buf* in, uint32_t n_in) {
-  return submit(s, dst, sender, args, args_bytes, in, n_in, nullptr, 0, nullptr, false, nullptr,
-                0);
+  try {
+    return submit(s, dst, sender, args, args_bytes, in, n_in, nullptr, 0, nullptr, false,
+                  nullptr, 0);
+  } catch (...) {  // host memory exhausted: no exception crosses the C ABI
+    return CAF_E_OVERLOAD;
+  }
 }
 
 int caf_gpu_request(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
@@ -1145,8 +1164,12 @@ int caf_gpu_request(caf_gpu_system* s, caf_actor dst, uint32_t sender, const voi
                     const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut) {
   if (!fut) return CAF_E_INVALID;
   *fut = nullptr;
-  return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut, true,
-                nullptr, 0);
+  try {
+    return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut,
+                  true, nullptr, 0);
+  } catch (...) {  // host memory exhausted: no exception crosses the C ABI
+    return CAF_E_OVERLOAD;
+  }
 }
 
 int caf_future_poll(caf_future* f, caf_buf* result, int32_t* reply_status) {
@@ -1272,7 +1295,7 @@ int caf_gpu_shutdown(caf_gpu_system* s) {
   if (s->poller.joinable()) s->poller.join();
   // Anything left never reached the device: answer it.  Futures the caller
   // still holds stay readable and are freed by caf_future_release.
-  for (uint32_t i = 0; i < s->cap; ++i) {
+  for (size_t i = 0; i < s->slots.size(); ++i) {
     SlotInfo& si = s->slots[i];
     if (!si.req_id) continue;
     if (si.fut) {
