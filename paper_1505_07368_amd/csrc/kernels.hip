@@ -9,24 +9,27 @@
 //
 //  * drain_kernel -- the mailbox drain.  Messages sit in a host-written
 //    mailbox ring (pinned, coherent host memory).  A workgroup that finds
-//    no claimable work takes the drain lock, reads the ring tail, copies up
+//    no claimable work (one of a few sentinels, or one that just finished
+//    work, holds a reservation or sees a backlog: see drain_body) takes the
+//    drain lock, reads the ring tail, copies up
 //    to max_batch entries (the paper's max_msgs per scheduling slot, Sec. 6)
 //    into device-resident slots, checks each actor is alive, groups the
 //    batch (by behaviour, largest GEMMs first, or mailbox order), prefix-sums
 //    the per-message work-tile counts into one global tile sequence and
 //    publishes it.  Every workgroup claims tiles of that sequence with a
 //    fetch_add on a claim cursor (see "claiming work tiles" below), and no
-//    workgroup ever waits for one that may not be resident.  The
+//    workgroup ever waits for one that may not be resident; consecutive
+//    claimed tiles of one GEMM run as one stream of k slices.  The
 //    workgroup finishing a message's last tile either publishes its reply
 //    (a completion record in host memory, released at system scope) or
 //    forwards the reply to the next actor of a pipeline on the device (no
 //    host round trip): a stage of at most kInlineStageTiles tiles runs in
 //    that workgroup at once, a larger one is published as new work tiles.
 //
-//    A launch retires as a whole once it has been idle for idle_ticks with
-//    an empty mailbox (batched mode: tens of microseconds, so one launch
-//    serves one burst; persistent mode: a long idle period) or at the stop
-//    flag.  Launches alternate between two streams, so a new launch can
+//    A launch retires as a whole once the published and drained counts
+//    have stood still for idle_ticks with an empty mailbox (batched mode:
+//    tens of microseconds, so one launch serves one burst; persistent mode:
+//    a long idle period) or at the stop flag.  Launches alternate between two streams, so a new launch can
 //    start while the previous one finishes its last tiles; launches share
 //    all counters and cooperate.  Every device-side wait is bounded by
 //    wait_ticks of the wall clock.
