@@ -13,11 +13,14 @@
 //
 // Concurrency: one mutex (`mu`) guards the actor table, the slot pool, the
 // arena and the ring writer; a request takes it once in the common case.
-// The poller never takes it: finished slots and unreferenced futures go onto
-// two lock-free stacks, and each later request returns a few of them to the
-// slot pool, the future pool and the arena (all of them when it would
-// otherwise be refused).  A contended mutex hand-off costs the poller a
-// sleep and a wake-up per batch of completions.
+// The poller never takes it: finished slots go into a ring that only the
+// poller appends to, unreferenced futures onto a lock-free stack, and each
+// later request returns a few of them to the slot pool, the future pool and
+// the arena (all of them when it would otherwise be refused).  A contended
+// mutex hand-off costs the poller a sleep and a wake-up per batch of
+// completions.  Fields written by the submitting side and by the poller sit
+// on separate cache lines, and the poller's view of a slot is kept apart
+// from the arena blocks only the submitting side reads.
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
@@ -196,12 +199,18 @@ struct caf_future {
   bool pooled = false;
 };
 
-struct SlotInfo {
+// What the poller needs of a slot (written at submit, cleared by the poller;
+// one line per slot so neighbouring slots do not share it).
+struct alignas(64) SlotInfo {
   uint64_t req_id = 0;
   caf_future* fut = nullptr;
+};
+
+// What only the submitting side needs of a slot (under mu): the arena blocks
+// to return when the slot is reclaimed.
+struct SlotTemps {
   Block temps[kMaxTemps];  // staged inputs, intermediate and unwanted replies
   uint32_t ntemps = 0;
-  uint32_t next_retired = 0;  // slot + 1 below this one on the retired-slot stack
 };
 
 // An instantiated graph of one message's plain launches (one kernel node per
@@ -232,38 +241,50 @@ struct caf_gpu_system {
   DevActor* dactors = nullptr;
   KArgs kargs{};
   uint32_t cap = 0;
+  // The submitting threads and the poller thread each write their own group
+  // of fields below; the groups, and every field both sides write, start on
+  // their own 64-byte line, so a completion does not evict the submit
+  // path's lines (the lock, the ring tail, the pools).
   // guarded by mu
-  std::mutex mu;
+  alignas(64) std::mutex mu;
   std::condition_variable cv_space;
   Arena arena;
   std::vector<ActorRec> actors;
   std::vector<SlotInfo> slots;
+  std::vector<SlotTemps> slot_temps;
   std::vector<uint32_t> free_slots;
   std::vector<caf_future*> fut_pool;
   std::vector<caf_future*> all_futs;  // every future object, for shutdown
   uint64_t tail = 0;
   uint64_t req_seq = 1;
   bool shut = false;
-  std::atomic<uint64_t> outstanding{0};
-  std::atomic<uint32_t> waiters{0};
-  // Returned without mu: pushed by any thread, emptied whole under mu.
-  std::atomic<uint32_t> retired_slots{0};  // slot + 1 of the top entry, 0 if empty
-  std::atomic<caf_future*> retired_futs{nullptr};
-  std::vector<uint32_t> pend_slots;        // taken off the stacks, not yet returned (mu)
+  std::vector<uint32_t> pend_slots;        // retired, not yet returned (mu)
   std::vector<caf_future*> pend_futs;
+  // Finished slots: the poller appends (single producer), reclaim() takes
+  // them in order under mu.  Every slot is in it at most once, so a power
+  // of two >= the slot count never overflows.
+  std::vector<uint32_t> retired_ring;
+  uint64_t retired_head = 0;  // mu
+  std::atomic<uint64_t> st_requests{0}, st_sends{0}, st_launches{0}, st_rejected{0};
+  // written by both sides
+  alignas(64) std::atomic<uint64_t> outstanding{0};
+  alignas(64) std::atomic<uint32_t> waiters{0};
+  alignas(64) std::atomic<uint64_t> retired_tail{0};  // poller
+  // Returned without mu: pushed by any thread, emptied whole under mu.
+  alignas(64) std::atomic<caf_future*> retired_futs{nullptr};
   // drain kernel
-  std::mutex launch_mu;
+  alignas(64) std::mutex launch_mu;
   std::atomic<uint32_t> launched_gen{0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
+  std::atomic<uint64_t> st_drain_launches{0};
   // poller
-  std::thread poller;
+  alignas(64) std::thread poller;
   std::atomic<bool> stop_poller{false};
   uint64_t comp_head = 0;
   uint32_t ccap = 0;  // completion ring entries (power of two)
-  std::atomic<uint64_t> st_requests{0}, st_sends{0}, st_completions{0}, st_launches{0},
-      st_drain_launches{0}, st_dup{0}, st_swallowed{0}, st_rejected{0};
-  uint32_t mandel_tile_px = 1024;
+  std::atomic<uint64_t> st_completions{0}, st_dup{0}, st_swallowed{0};
+  alignas(64) uint32_t mandel_tile_px = 1024;
   uint32_t gemm_tile = 0;
   uint32_t grid_full = 0, grid_light = 0;  // drain-kernel workgroups per variant
   std::atomic<bool> need_full{false};       // a GEMM actor exists
@@ -304,15 +325,6 @@ caf_future* new_future(caf_gpu_system* s) {  // mu held
   return f;
 }
 
-// Pushes a finished slot (poller thread; its SlotInfo is no longer read by
-// anyone else until reclaim() returns it to the pool).
-void retire_slot(caf_gpu_system* s, uint32_t slot) {
-  uint32_t top = s->retired_slots.load(std::memory_order_relaxed);
-  do {
-    s->slots[slot].next_retired = top;
-  } while (!s->retired_slots.compare_exchange_weak(top, slot + 1, std::memory_order_release,
-                                                   std::memory_order_relaxed));
-}
 
 void put_ref(caf_future* f) {  // mu not held
   if (f->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
@@ -331,26 +343,26 @@ void put_ref(caf_future* f) {  // mu not held
 }
 
 // Returns up to `budget` retired slots and as many futures, with their
-// arena blocks, to the pools (mu held).  Both stacks are taken whole into
-// pending lists, so a push racing with this one simply waits for the next
-// call; the budget spreads the work of a large burst of completions over
-// the requests that follow instead of stalling one of them.
+// arena blocks, to the pools (mu held).  The retired slots published so far
+// and the whole retired-future stack are moved to pending lists, so a push
+// racing with this one simply waits for the next call; the budget spreads
+// the work of a large burst of completions over the requests that follow
+// instead of stalling one of them.
 constexpr size_t kReclaimBudget = 16;
 constexpr size_t kReclaimAll = ~size_t(0);
 
 bool reclaim_pending(const caf_gpu_system* s) {
   return !s->pend_slots.empty() || !s->pend_futs.empty() ||
-         s->retired_slots.load(std::memory_order_relaxed) ||
+         s->retired_head != s->retired_tail.load(std::memory_order_relaxed) ||
          s->retired_futs.load(std::memory_order_relaxed);
 }
 
 void reclaim(caf_gpu_system* s, size_t budget) {
-  if (s->retired_slots.load(std::memory_order_relaxed)) {
-    uint32_t top = s->retired_slots.exchange(0, std::memory_order_acquire);
-    while (top) {
-      s->pend_slots.push_back(top - 1);
-      top = s->slots[top - 1].next_retired;
-    }
+  {
+    const uint64_t tl = s->retired_tail.load(std::memory_order_acquire);
+    const uint64_t mask = s->retired_ring.size() - 1;
+    for (; s->retired_head < tl; ++s->retired_head)
+      s->pend_slots.push_back(s->retired_ring[s->retired_head & mask]);
   }
   if (s->retired_futs.load(std::memory_order_relaxed)) {
     caf_future* f = s->retired_futs.exchange(nullptr, std::memory_order_acquire);
@@ -362,9 +374,9 @@ void reclaim(caf_gpu_system* s, size_t budget) {
   for (size_t n = 0; n < budget && !s->pend_slots.empty(); ++n) {
     const uint32_t slot = s->pend_slots.back();
     s->pend_slots.pop_back();
-    SlotInfo& si = s->slots[slot];
-    for (uint32_t k = 0; k < si.ntemps; ++k) s->arena.free(si.temps[k].addr, si.temps[k].bytes);
-    si.ntemps = 0;
+    SlotTemps& st = s->slot_temps[slot];
+    for (uint32_t k = 0; k < st.ntemps; ++k) s->arena.free(st.temps[k].addr, st.temps[k].bytes);
+    st.ntemps = 0;
     s->free_slots.push_back(slot);
   }
   for (size_t n = 0; n < budget && !s->pend_futs.empty(); ++n) {
@@ -428,6 +440,8 @@ void resolve_batch(caf_gpu_system* s, const Comp* recs, uint32_t n) {
   caf_future* futs[kPollBatch];
   const Comp* frec[kPollBatch];
   uint32_t nf = 0, valid = 0;
+  uint64_t rt = s->retired_tail.load(std::memory_order_relaxed);  // this thread's own
+  const uint64_t rmask = s->retired_ring.size() - 1;
   // A slot's record was written under mu before its ring entry was
   // published, and stays the poller's from its completion until reclaim()
   // hands the slot out again; clearing req_id makes a repeated record for it
@@ -447,9 +461,12 @@ void resolve_batch(caf_gpu_system* s, const Comp* recs, uint32_t n) {
     }
     si.fut = nullptr;
     si.req_id = 0;
-    retire_slot(s, slot);
+    s->retired_ring[rt++ & rmask] = slot;
     ++valid;
   }
+  // the slots go back after their records are consumed (release: reclaim
+  // sees the cleared fields)
+  s->retired_tail.store(rt, std::memory_order_release);
   s->st_completions += valid;
   const int64_t t = now_ns();
   for (uint32_t i = 0; i < nf; ++i) {
@@ -878,11 +895,12 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
   SlotInfo& si = s->slots[slot];
   si.req_id = rid;
   si.fut = f;
-  si.ntemps = 0;
+  SlotTemps& stt = s->slot_temps[slot];
+  stt.ntemps = 0;
   for (auto& b : staged)
-    if (b.bytes) si.temps[si.ntemps++] = b;
+    if (b.bytes) stt.temps[stt.ntemps++] = b;
   for (uint32_t k = 0; k <= nhops; ++k)
-    if (sout[k].bytes && !(f && k == nhops)) si.temps[si.ntemps++] = sout[k];
+    if (sout[k].bytes && !(f && k == nhops)) stt.temps[stt.ntemps++] = sout[k];
   if (f) {
     f->req_id = rid;
     f->t_issue = now_ns();
@@ -1059,6 +1077,10 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   try {
     s->actors.reserve(kMaxActors);
     s->slots.resize(cap);
+    s->slot_temps.resize(cap);
+    size_t rcap = 1;
+    while (rcap < cap) rcap <<= 1;
+    s->retired_ring.resize(rcap);
     s->free_slots.reserve(cap);
     s->pend_slots.reserve(cap);
   } catch (...) {  // no exception crosses the C ABI
