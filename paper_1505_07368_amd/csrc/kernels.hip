@@ -493,22 +493,31 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
 __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
   const uint32_t t = threadIdx.x;
   // One PCIe round trip: the ring tail, the stop flag and a snapshot of the
-  // actors' alive bits are read together.  The snapshot is not ordered after
-  // the tail read, so a bit the host set just before publishing an entry can
-  // be missing from it; entries that look dead are checked again below.
-  if (t < kAliveWords) L.alive[t] = ld_sys(&a.hctl->alive[t]);
+  // actors' alive bits are read together (the snapshot by the second wave,
+  // so that thread 0 does not wait for it before issuing its own loads).
+  // The snapshot is not ordered after the tail read, so a bit the host set
+  // just before publishing an entry can be missing from it; entries that
+  // look dead are checked again below.
+  static_assert(kAliveWords <= 64, "one wave reads the alive words");
+  if (t >= 64 && t < 64 + kAliveWords) L.alive[t - 64] = ld_sys(&a.hctl->alive[t - 64]);
   if (t == 0) L.any_dead = 0;
   if (t == 0) {
-    const uint64_t tail = ld_sys_acq(&a.hctl->tail);
+    // All five loads are in flight together; one system-scope acquire fence
+    // after them orders the entry reads below after the tail (each acquire
+    // load on its own would wait for its own round trip).
     const uint32_t stop = ld_sys(&a.hctl->stop);
-    const uint64_t d = ld_dev_acq(&a.dctl->drained);
+    const uint64_t tail = ld_sys(&a.hctl->tail);
+    const uint64_t d = ld_dev(&a.dctl->drained);
+    const uint64_t pubv = ld_dev(&a.dctl->tiles_pub);
+    const uint64_t done = ld_dev(&a.dctl->tiles_done);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     const uint64_t avail = tail - d;
     L.d = d;
     L.cnt = avail < a.max_batch ? avail : a.max_batch;
     // Lets idle workgroups help while a backlog remains (relaxed: a hint).
     st_dev(&a.dctl->backlog, avail > a.max_batch ? 1u : 0u);
-    L.pub = ld_dev_acq(&a.dctl->tiles_pub);
-    L.done = ld_dev_acq(&a.dctl->tiles_done);
+    L.pub = pubv;
+    L.done = done;
     if (stop) st_dev(&a.dctl->stop_seen, 1u);
   }
   if (t < kKeys) L.hist[t] = 0;
@@ -521,15 +530,16 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
   }
   // Copy the entries into their device slots.
   for (uint32_t i = t; i < cnt; i += kThreads) {
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(&a.hring[(L.d + i) % a.cap]);
-    Desc e;
-    uint64_t* dst = reinterpret_cast<uint64_t*>(&e);
-    // In two halves, so at most 64 bytes of the entry are in flight per lane.
+    // Plain 16-byte loads (eight PCIe reads per entry): the host wrote the
+    // entry before the tail, and the acquire fence after the tail read
+    // dropped any cached copy of it.
+    const auto src = global_ptr(reinterpret_cast<const uint32_t*>(&a.hring[(L.d + i) % a.cap]));
+    struct Raw {
+      uint4 q[sizeof(Desc) / 16];
+    } raw;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) dst[q] = ld_sys(src + q);
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int q = 8; q < 16; ++q) dst[q] = ld_sys(src + q);
+    for (int q = 0; q < (int)(sizeof(Desc) / 16); ++q) raw.q[q] = load_global<uint4>(src + 4 * q);
+    const Desc e = __builtin_bit_cast(Desc, raw);
     const bool alive = (L.alive[e.actor >> 5] >> (e.actor & 31)) & 1u;
     const uint32_t slot = e.slot;
     a.slots[slot].d = e;
@@ -570,67 +580,82 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
     }
   }
   // Flow control: keep the tile map ahead of the slowest reader by half its size.
-  for (uint32_t i = t; i < cnt; i += kThreads) L.scan[i] = L.nt[i];
-  __syncthreads();
-  uint32_t total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
   const uint64_t room = kTileMapCap / 2 - (L.pub - L.done);
-  if (total > room) {
-    if (t == 0) {
-      uint32_t c = 0;
-      while (c < cnt && (uint64_t)L.scan[c] + L.nt[c] <= room) ++c;
-      L.cnt = c;
-    }
-    __syncthreads();
-    cnt = (uint32_t)L.cnt;
-    if (cnt == 0) {
+  uint32_t total;
+  if (cnt == 1) {
+    // A single entry (the common case at low load): no scan, no grouping.
+    total = L.nt[0];
+    if (total > room) {
       if (t == 0) unlock_drain(a);
       return false;
     }
-  }
-  // Grouping: stable counting sort of the batch by key.
-  if (a.grouping == CAF_GROUP_LPT) {
-    for (uint32_t i = t; i < cnt; i += kThreads) atomicAdd(&L.hist[L.key[i]], 1u);
-    __syncthreads();
     if (t == 0) {
-      uint32_t run = 0;
-      for (uint32_t k = 0; k < kKeys; ++k) {
-        L.running[k] = run;
-        run += L.hist[k];
-      }
+      L.pos[0] = 0;
+      L.scan[0] = 0;
     }
     __syncthreads();
-    const uint32_t lane = lane_id(), w = wave_id();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint32_t c0 = 0; c0 < cnt; c0 += kThreads) {
-      const uint32_t i = c0 + t;
-      const bool valid = i < cnt;
-      const uint32_t k = valid ? L.key[i] : kKeys;
-      uint32_t rank = 0;
-      for (uint32_t kk = 0; kk < kKeys; ++kk) {
-        const uint64_t m = __ballot(valid && k == kk);
-        if (k == kk) rank = __popcll(m & lt_mask);
-        if (lane == 0) L.wave_cnt[w][kk] = __popcll(m);
-      }
-      __syncthreads();
-      uint32_t off = 0;
-      if (valid) {
-        off = L.running[k];
-        for (uint32_t ww = 0; ww < w; ++ww) off += L.wave_cnt[ww][k];
-      }
-      __syncthreads();
-      if (t < kKeys)
-        for (uint32_t ww = 0; ww < 4; ++ww) L.running[t] += L.wave_cnt[ww][t];
-      if (valid) L.pos[i] = (uint16_t)(off + rank);
-      __syncthreads();
-    }
   } else {
-    for (uint32_t i = t; i < cnt; i += kThreads) L.pos[i] = (uint16_t)i;
-  }
-  __syncthreads();
-  // Prefix of tile counts in work order.
-  for (uint32_t i = t; i < cnt; i += kThreads) L.scan[L.pos[i]] = L.nt[i];
-  __syncthreads();
-  total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
+    for (uint32_t i = t; i < cnt; i += kThreads) L.scan[i] = L.nt[i];
+    __syncthreads();
+    total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
+    if (total > room) {
+      if (t == 0) {
+        uint32_t c = 0;
+        while (c < cnt && (uint64_t)L.scan[c] + L.nt[c] <= room) ++c;
+        L.cnt = c;
+      }
+      __syncthreads();
+      cnt = (uint32_t)L.cnt;
+      if (cnt == 0) {
+        if (t == 0) unlock_drain(a);
+        return false;
+      }
+    }
+    // Grouping: stable counting sort of the batch by key.
+    if (a.grouping == CAF_GROUP_LPT) {
+      for (uint32_t i = t; i < cnt; i += kThreads) atomicAdd(&L.hist[L.key[i]], 1u);
+      __syncthreads();
+      if (t == 0) {
+        uint32_t run = 0;
+        for (uint32_t k = 0; k < kKeys; ++k) {
+          L.running[k] = run;
+          run += L.hist[k];
+        }
+      }
+      __syncthreads();
+      const uint32_t lane = lane_id(), w = wave_id();
+      const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      for (uint32_t c0 = 0; c0 < cnt; c0 += kThreads) {
+        const uint32_t i = c0 + t;
+        const bool valid = i < cnt;
+        const uint32_t k = valid ? L.key[i] : kKeys;
+        uint32_t rank = 0;
+        for (uint32_t kk = 0; kk < kKeys; ++kk) {
+          const uint64_t m = __ballot(valid && k == kk);
+          if (k == kk) rank = __popcll(m & lt_mask);
+          if (lane == 0) L.wave_cnt[w][kk] = __popcll(m);
+        }
+        __syncthreads();
+        uint32_t off = 0;
+        if (valid) {
+          off = L.running[k];
+          for (uint32_t ww = 0; ww < w; ++ww) off += L.wave_cnt[ww][k];
+        }
+        __syncthreads();
+        if (t < kKeys)
+          for (uint32_t ww = 0; ww < 4; ++ww) L.running[t] += L.wave_cnt[ww][t];
+        if (valid) L.pos[i] = (uint16_t)(off + rank);
+        __syncthreads();
+      }
+    } else {
+      for (uint32_t i = t; i < cnt; i += kThreads) L.pos[i] = (uint16_t)i;
+    }
+    __syncthreads();
+    // Prefix of tile counts in work order.
+    for (uint32_t i = t; i < cnt; i += kThreads) L.scan[L.pos[i]] = L.nt[i];
+    __syncthreads();
+    total = block_exclusive_scan(L.scan, cnt, L.wave_sum);
+  }  // cnt > 1
   const uint64_t pub = L.pub;
   for (uint32_t i = t; i < cnt; i += kThreads) {
     const uint32_t slot = L.slot[i], nt = L.nt[i];
