@@ -226,21 +226,24 @@ __device__ __forceinline__ bool stage_done(KArgsC& a, const Desc& d, bool ring) 
   return false;
 }
 
-// Accounts one finished tile of message `d` (thread 0, after the
+// Accounts `count` finished tiles of message `d` (thread 0, after the
 // workgroup's tile work is complete).  The last tile of a message resets
 // the slot's counters and completes or forwards it; returns true if the
-// workgroup is to run the next pipeline stage inline.
-// Counts `count` finished tiles of the message (thread 0).
+// workgroup is to run the next pipeline stage inline.  A workgroup that ran
+// every tile of the stage itself (a one-tile message, or a whole GEMM run)
+// skips the shared count: no other workgroup's work has to be waited for.
 __device__ __forceinline__ bool finish_tiles(KArgsC& a, const Desc& d, uint32_t ntiles,
                                              uint32_t count, bool ring) {
   const uint32_t slot = d.slot;
   SlotState* ss = &a.sstate[slot];
   bool cont = false;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  const uint32_t prev = __hip_atomic_fetch_add(&ss->done, count, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+  const bool whole = count == ntiles;
+  const uint32_t prev =
+      whole ? 0u
+            : __hip_atomic_fetch_add(&ss->done, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (prev + count == ntiles) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!whole) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     st_dev(&ss->done, 0u);
     st_dev(&ss->decision, 0u);
     cont = stage_done(a, d, ring);
