@@ -112,11 +112,10 @@ __device__ __forceinline__ bool actor_alive(const HostCtl* h, uint32_t actor) {
 
 // ---- completion -------------------------------------------------------------
 
-// Publishes one reply notification to the host (thread-level).
-__device__ void write_completion(KArgsC& a, uint64_t req_id, int32_t status,
-                                 const uint8_t* data) {
-  const uint64_t pos = __hip_atomic_fetch_add(&a.dctl->comp_tail, (uint64_t)1,
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Publishes one reply notification to the host at completion position
+// `pos` (thread-level).
+__device__ void write_completion_at(KArgsC& a, uint64_t pos, uint64_t req_id, int32_t status,
+                                    const uint8_t* data) {
   Comp* c = &a.comp[pos & (a.ccap - 1u)];  // ccap is a power of two
   st_sys(&c->req_id, req_id);
   st_sys(&c->status, status);
@@ -127,6 +126,14 @@ __device__ void write_completion(KArgsC& a, uint64_t req_id, int32_t status,
     st_sys(dst + i, v);
   }
   st_sys_rel(&c->lap, (uint32_t)(pos >> __builtin_ctz(a.ccap)) + 1u);
+}
+
+// Publishes one reply notification at the next completion position.
+__device__ void write_completion(KArgsC& a, uint64_t req_id, int32_t status,
+                                 const uint8_t* data) {
+  const uint64_t pos = __hip_atomic_fetch_add(&a.dctl->comp_tail, (uint64_t)1,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  write_completion_at(a, pos, req_id, status, data);
 }
 
 // Appends `nt` tiles of slot `slot` to the global tile sequence (caller
@@ -443,6 +450,14 @@ struct DrainLds {
   uint16_t pos[kMaxBatch];
   uint8_t key[kMaxBatch];
   uint8_t dead[kMaxBatch];
+  // hash-chain entries the drain runs itself: actor + 1 (0: not one), the
+  // new state, and the list of entries run
+  uint16_t hactor[kMaxBatch];
+  uint64_t hx[kMaxBatch];
+  uint16_t hidx[kMaxBatch];
+  uint32_t nh;
+  uint32_t any_hash;  // some entry is one
+  uint64_t hpos;
   uint32_t first_bad;  // light launch: first entry it cannot run
   uint32_t any_dead;   // some entry's actor looked dead in the snapshot
   uint32_t alive[kAliveWords];
@@ -491,6 +506,65 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
   return total;
 }
 
+// Stateful hash-chain entries of entries [0, cnt) run here, in mailbox
+// order, by thread 0 while the drain lock is held: the state update is a
+// few instructions, and done by the drainer it needs no hand-off between
+// workgroups (a tile waiting for its predecessor's sequence number takes a
+// device round trip per step).  Per actor, entries run while their sequence
+// numbers continue the actor's; from the first that does not (an earlier
+// entry of the actor went the tile way) the rest go the tile way too, where
+// they wait their turn.  Entries run here get no tiles (nt = 0).
+__device__ void run_hash_entries_locked(KArgsC& a, DrainLds& L, uint32_t cnt) {
+  uint32_t nh = 0;
+  if (!L.any_hash) cnt = 0;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const uint32_t x1 = L.hactor[i];
+    if (x1 == 0) continue;
+    DevActor* act = &a.actors[x1 - 1u];
+    uint32_t next = ld_dev_acq(&act->seq_done);
+    uint64_t st = ld_dev(&act->state);
+    bool ok = true, any = false;
+    for (uint32_t j = i; j < cnt; ++j) {
+      if (L.hactor[j] != x1) continue;
+      L.hactor[j] = 0;
+      const Desc& e = a.slots[L.slot[j]].d;  // written by this workgroup this pass
+      if (!ok || e.seq != next) {
+        ok = false;
+        continue;
+      }
+      st = (st * 1000003ull) ^ e.p.h.x;
+      L.hx[j] = st;
+      L.hidx[nh++] = (uint16_t)j;
+      L.nt[j] = 0;
+      ++next;
+      any = true;
+    }
+    if (any) {
+      st_dev(&act->state, st);
+      st_dev_rel(&act->seq_done, next);
+    }
+  }
+  L.nh = nh;
+}
+
+// The replies of the entries run by run_hash_entries_locked: one completion
+// position reservation, then the records in parallel (whole workgroup).
+__device__ void complete_hash_entries(KArgsC& a, DrainLds& L) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t nh = L.nh;
+  if (nh == 0) return;
+  if (t == 0)
+    L.hpos = __hip_atomic_fetch_add(&a.dctl->comp_tail, (uint64_t)nh, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  for (uint32_t j = t; j < nh; j += kThreads) {
+    const uint32_t i = L.hidx[j];
+    const uint64_t v[2] = {L.hx[i], 0ull};
+    write_completion_at(a, L.hpos + j, a.slots[L.slot[i]].d.req_id, CAF_OK,
+                        reinterpret_cast<const uint8_t*>(v));
+  }
+}
+
 // Drains one batch from the mailbox (whole workgroup; the caller holds the
 // drain lock, which is released here).  Returns true if anything was drained.
 __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
@@ -504,6 +578,7 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
   static_assert(kAliveWords <= 64, "one wave reads the alive words");
   if (t >= 64 && t < 64 + kAliveWords) L.alive[t - 64] = ld_sys(&a.hctl->alive[t - 64]);
   if (t == 0) L.any_dead = 0;
+  if (t == 0) L.any_hash = 0;
   if (t == 0) {
     // All five loads are in flight together; one system-scope acquire fence
     // after them orders the entry reads below after the tail (each acquire
@@ -551,6 +626,10 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
     L.dead[i] = alive ? 0 : 1;
     if (!alive) L.any_dead = 1;
     L.key[i] = (uint8_t)(a.grouping == CAF_GROUP_LPT ? group_key(e) : 0u);
+    const bool hash_here = alive && e.behavior == CAF_BHV_HASHCHAIN && e.hop_actor[0] == 0 &&
+                           (e.flags & (DF_INLINE_OUT | DF_SEND)) != 0;
+    L.hactor[i] = hash_here ? (uint16_t)(e.actor + 1u) : (uint16_t)0;
+    if (hash_here) L.any_hash = 1;
     if (!a.full && e.behavior == CAF_BHV_GEMM) atomicMin(&L.first_bad, i);
   }
   __syncthreads();
@@ -587,16 +666,17 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
   uint32_t total;
   if (cnt == 1) {
     // A single entry (the common case at low load): no scan, no grouping.
-    total = L.nt[0];
-    if (total > room) {
+    if (L.nt[0] > room) {
       if (t == 0) unlock_drain(a);
       return false;
     }
     if (t == 0) {
+      run_hash_entries_locked(a, L, 1);
       L.pos[0] = 0;
       L.scan[0] = 0;
     }
     __syncthreads();
+    total = L.nt[0];
   } else {
     for (uint32_t i = t; i < cnt; i += kThreads) L.scan[i] = L.nt[i];
     __syncthreads();
@@ -614,6 +694,8 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
         return false;
       }
     }
+    if (t == 0) run_hash_entries_locked(a, L, cnt);
+    __syncthreads();
     // Grouping: stable counting sort of the batch by key.
     if (a.grouping == CAF_GROUP_LPT) {
       for (uint32_t i = t; i < cnt; i += kThreads) atomicAdd(&L.hist[L.key[i]], 1u);
@@ -668,6 +750,7 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
     for (uint32_t k = 0; k < nt; ++k) a.tile2slot[(base + k) & (kTileMapCap - 1)] = slot;
     if (L.dead[i]) write_completion(a, a.slots[slot].d.req_id, CAF_E_QUIT, nullptr);
   }
+  complete_hash_entries(a, L);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (t == 0) {

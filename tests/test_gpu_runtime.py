@@ -50,6 +50,41 @@ def test_fifo_hash_chain_three_senders(sysm):
         assert st == cg.OK and int(v[0]) == state
 
 
+def test_hash_chains_interleaved_with_sends_and_echo(sysm):
+    """Two stateful actors whose messages are interleaved in the mailbox
+    with sends (no reply) and echo requests: each actor's state follows its
+    own messages in mailbox order (Sec. 2: one mailbox per actor, FIFO), so
+    a drain pass holding entries of both applies each chain in order."""
+    from paper_1505_07368_amd import binding as cg
+    acts = [sysm.spawn(cg.BHV_HASHCHAIN), sysm.spawn(cg.BHV_HASHCHAIN)]
+    e = sysm.spawn(cg.BHV_NOOP)
+    g = gen.rng(9)
+    state = [0, 0]
+    checks, echoes = [], []
+    for i in range(600):
+        k = int(g.integers(0, 3))
+        if k == 2:
+            x = np.array([i], np.int32)
+            echoes.append((i, sysm.request(e, inputs=[x])))
+            continue
+        x = int(g.integers(0, 2 ** 62))
+        state[k] = oracle.hash_step(state[k], x)
+        if g.integers(0, 4) == 0:
+            assert sysm.send(acts[k], cg.caf_hash_args(x)) == cg.OK
+        else:
+            checks.append((state[k], sysm.request(acts[k], cg.caf_hash_args(x))))
+    for want, f in checks:
+        st, v = f.result()
+        assert st == cg.OK and int(v[0]) == want
+    for i, f in echoes:
+        st, v = f.result()
+        assert st == cg.OK and int(v[0]) == i
+    # the chains continue from the state the sends advanced
+    for k in range(2):
+        st, v = sysm.request(acts[k], cg.caf_hash_args(7)).result()
+        assert st == cg.OK and int(v[0]) == oracle.hash_step(state[k], 7)
+
+
 def test_exactly_once_and_sends(sysm):
     from paper_1505_07368_amd import binding as cg
     before = sysm.stats()
