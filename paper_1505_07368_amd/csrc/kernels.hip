@@ -16,10 +16,12 @@
 //    into device-resident slots, checks each actor is alive, groups the
 //    batch (by behaviour, largest GEMMs first, or mailbox order), prefix-sums
 //    the per-message work-tile counts into one global tile sequence and
-//    publishes it.  Every workgroup claims tiles of that sequence with a
-//    fetch_add on a claim cursor (see "claiming work tiles" below), and no
-//    workgroup ever waits for one that may not be resident; consecutive
-//    claimed tiles of one GEMM run as one stream of k slices.  The
+//    publishes it (the drainer reserving first).  Every workgroup claims
+//    tiles of that sequence with a fetch_add on a claim cursor (see
+//    "claiming work tiles" below), and no workgroup ever waits for one that
+//    may not be resident; consecutive claimed tiles of one GEMM run as one
+//    stream of k slices.  Stateful hash-chain entries are applied by the
+//    drainer itself, in mailbox order, while it holds the lock.  The
 //    workgroup finishing a message's last tile either publishes its reply
 //    (a completion record in host memory, released at system scope) or
 //    forwards the reply to the next actor of a pipeline on the device (no
@@ -29,15 +31,16 @@
 //    A launch retires as a whole once the published and drained counts
 //    have stood still for idle_ticks with an empty mailbox (batched mode:
 //    tens of microseconds, so one launch serves one burst; persistent mode:
-//    a long idle period) or at the stop flag.  Launches alternate between two streams, so a new launch can
-//    start while the previous one finishes its last tiles; launches share
-//    all counters and cooperate.  Every device-side wait is bounded by
-//    wait_ticks of the wall clock.
+//    a long idle period) or at the stop flag.  Launches alternate between
+//    two streams, so a new launch can start while the previous one finishes
+//    its last tiles; launches share all counters and cooperate.  Every
+//    device-side wait is bounded by wait_ticks of the wall clock.
 //
 // Requests are FIFO per (sender, actor) because the host appends to the
-// ring in call order and the drain preserves each actor's relative order;
-// stateful actors (the hash chain) additionally wait for their previous
-// message's sequence number before updating device-resident state.
+// ring in call order and the drain preserves each actor's relative order.
+// A stateful update (the hash chain) that runs as a tile -- one launch per
+// message, or an entry the drainer could not apply in sequence -- waits for
+// its predecessor's sequence number before touching device-resident state.
 #pragma clang fp contract(off)
 
 #include "caf_internal.h"
@@ -506,6 +509,27 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
   return total;
 }
 
+// A workgroup's reservation of claimed tile indices (see "claiming work
+// tiles" below).
+struct Claim {
+  uint64_t next = 0, end = 0;  // tiles [next, end) are this workgroup's
+  bool own = false;  // published by this workgroup's own drain pass
+};
+
+// Returns the published count it read (0 if it reserved nothing).
+__device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c) {
+  const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
+  const uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
+  if (cur >= pub) return 0;
+  // guided self-scheduling: large chunks while plenty is published
+  const uint64_t avail = pub - cur, g2 = 2ull * a.grid;
+  const uint64_t k = avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4 : avail >= 2 * g2 ? 2 : 1;
+  c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  c.end = c.next + k;
+  return pub;
+}
+
 // Stateful hash-chain entries of entries [0, cnt) run here, in mailbox
 // order, by thread 0 while the drain lock is held: the state update is a
 // few instructions, and done by the drainer it needs no hand-off between
@@ -567,7 +591,8 @@ __device__ void complete_hash_entries(KArgsC& a, DrainLds& L) {
 
 // Drains one batch from the mailbox (whole workgroup; the caller holds the
 // drain lock, which is released here).  Returns true if anything was drained.
-__device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
+__device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may_claim,
+                                                Claim& cl) {
   const uint32_t t = threadIdx.x;
   // One PCIe round trip: the ring tail, the stop flag and a snapshot of the
   // actors' alive bits are read together (the snapshot by the second wave,
@@ -758,6 +783,16 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
     // every thread, so the tiles are published first, without another fence.
     // The unlock releases the drained counts: the host copy must never move
     // backwards, so it lands before the next holder can write its own.
+    // The drainer takes one index before the tiles become visible, so it
+    // runs the first of them itself (a one-message pass is usually a reply
+    // waited for, and the slots and tile map it just wrote are in its L2);
+    // an index beyond them is an ordinary reservation.
+    if (total && may_claim) {
+      cl.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, (uint64_t)1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+      cl.end = cl.next + 1;
+      cl.own = cl.next >= pub && cl.next < pub + total;
+    }
     st_dev(&a.dctl->tiles_pub, pub + total);
     st_dev(&a.dctl->drained, L.d + cnt);
     st_sys(&a.hctl->drained, L.d + cnt);
@@ -769,12 +804,35 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L) {
 // The full variant keeps the drain out of line (its tile loop already needs
 // most registers); the light variant inlines it, so that the whole kernel is
 // allocated under its five-waves-per-SIMD register budget.
-CAF_RARE bool drain_once_outlined(KArgsC& a, DrainLds& L) { return drain_once_body(a, L); }
+// (Its result comes back by value, so the caller's reservation stays in
+// registers.)
+struct DrainOut {
+  uint64_t next, end;
+  bool own, got;
+};
+CAF_RARE DrainOut drain_once_outlined(KArgsC& a, DrainLds& L, bool may_claim) {
+  Claim cl;
+  const bool got = drain_once_body(a, L, may_claim, cl);
+  return DrainOut{cl.next, cl.end, cl.own, got};
+}
 
 template <bool kFull>
-__device__ __forceinline__ bool drain_once(KArgsC& a, DrainLds& L) {
-  if constexpr (kFull) return drain_once_outlined(a, L);
-  else return drain_once_body(a, L);
+__device__ __forceinline__ bool drain_once(KArgsC& a, DrainLds& L, Claim& c) {
+  // thread 0 may come back with a reservation of the tiles just published
+  if constexpr (kFull) {
+    const DrainOut r = drain_once_outlined(a, L, c.next == c.end);
+    if (r.end > r.next) {
+      c.next = r.next;
+      c.end = r.end;
+      c.own = r.own;
+    }
+    return r.got;
+  } else {
+    Claim cl;
+    const bool got = drain_once_body(a, L, c.next == c.end, cl);
+    if (cl.end > cl.next) c = cl;
+    return got;
+  }
 }
 
 // ---- claiming work tiles ----------------------------------------------
@@ -789,24 +847,6 @@ __device__ __forceinline__ bool drain_once(KArgsC& a, DrainLds& L) {
 // leaves (retire or stop), holders of unfilled reservations publish filler
 // tiles for every reserved index, so no index is ever abandoned and no
 // message tile is ever skipped.
-
-struct Claim {
-  uint64_t next = 0, end = 0;  // tiles [next, end) are this workgroup's
-};
-
-// Returns the published count it read (0 if it reserved nothing).
-__device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c) {
-  const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
-  const uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
-  if (cur >= pub) return 0;
-  // guided self-scheduling: large chunks while plenty is published
-  const uint64_t avail = pub - cur, g2 = 2ull * a.grid;
-  const uint64_t k = avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4 : avail >= 2 * g2 ? 2 : 1;
-  c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  c.end = c.next + k;
-  return pub;
-}
 
 // Publishes filler tiles for every reserved but unpublished index (caller
 // holds the drain lock).
@@ -845,7 +885,16 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
       uint32_t cmd = CMD_IDLE;
       uint64_t pub = 0;
       if (c.next == c.end) pub = reserve(a, c);
-      if (c.next < c.end) {
+      if (c.next < c.end && c.own) {
+        // An index of this workgroup's own drain pass: published, its slot
+        // and tile map entry are this workgroup's writes, and the pass's
+        // system-scope acquire already covers the message's data.
+        s_g = c.next;
+        s_k = (uint32_t)(c.end - c.next);
+        c.next = c.end;
+        c.own = false;
+        cmd = CMD_TILE;
+      } else if (c.next < c.end) {
         // the count read while reserving usually covers the new indices
         if (c.next >= pub) pub = ld_dev(&a.dctl->tiles_pub);
         if (c.next < pub) {
@@ -918,7 +967,7 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
       continue;
     }
     if (cmd == CMD_DRAIN) {
-      const bool got = drain_once<kFull>(a, *reinterpret_cast<DrainLds*>(smem));
+      const bool got = drain_once<kFull>(a, *reinterpret_cast<DrainLds*>(smem), c);
       __syncthreads();
       if (got) {
         last_work = now_ticks();
