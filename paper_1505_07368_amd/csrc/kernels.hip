@@ -531,44 +531,63 @@ __device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c) {
 }
 
 // Stateful hash-chain entries of entries [0, cnt) run here, in mailbox
-// order, by thread 0 while the drain lock is held: the state update is a
-// few instructions, and done by the drainer it needs no hand-off between
+// order, while the drain lock is held: the state update is a few
+// instructions, and done by the drainer it needs no hand-off between
 // workgroups (a tile waiting for its predecessor's sequence number takes a
 // device round trip per step).  Per actor, entries run while their sequence
 // numbers continue the actor's; from the first that does not (an earlier
 // entry of the actor went the tile way) the rest go the tile way too, where
-// they wait their turn.  Entries run here get no tiles (nt = 0).
+// they wait their turn.  Entries run here get no tiles (nt = 0).  Wave 0
+// finds each actor's entries 64 at a time with ballots; lane 0 applies them.
 __device__ void run_hash_entries_locked(KArgsC& a, DrainLds& L, uint32_t cnt) {
-  uint32_t nh = 0;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t nh = 0;  // lane 0's count
   if (!L.any_hash) cnt = 0;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const uint32_t x1 = L.hactor[i];
-    if (x1 == 0) continue;
-    DevActor* act = &a.actors[x1 - 1u];
-    uint32_t next = ld_dev_acq(&act->seq_done);
-    uint64_t st = ld_dev(&act->state);
-    bool ok = true, any = false;
-    for (uint32_t j = i; j < cnt; ++j) {
-      if (L.hactor[j] != x1) continue;
-      L.hactor[j] = 0;
-      const Desc& e = a.slots[L.slot[j]].d;  // written by this workgroup this pass
-      if (!ok || e.seq != next) {
-        ok = false;
-        continue;
+  for (uint32_t c0 = 0; c0 < cnt; c0 += 64) {
+    for (;;) {
+      const uint32_t j = c0 + lane;
+      const uint64_t m = __ballot(j < cnt && L.hactor[j] != 0);
+      if (m == 0) break;
+      // the first entry not handled yet starts its actor's chain
+      const uint32_t x1 = L.hactor[c0 + (uint32_t)__builtin_ctzll(m)];
+      DevActor* act = &a.actors[x1 - 1u];
+      uint32_t next = 0;
+      uint64_t st = 0;
+      bool ok = true, any = false;
+      if (lane == 0) {
+        next = ld_dev_acq(&act->seq_done);
+        st = ld_dev(&act->state);
       }
-      st = (st * 1000003ull) ^ e.p.h.x;
-      L.hx[j] = st;
-      L.hidx[nh++] = (uint16_t)j;
-      L.nt[j] = 0;
-      ++next;
-      any = true;
-    }
-    if (any) {
-      st_dev(&act->state, st);
-      st_dev_rel(&act->seq_done, next);
+      for (uint32_t d0 = c0; d0 < cnt; d0 += 64) {
+        const uint32_t jj = d0 + lane;
+        const bool mine = jj < cnt && L.hactor[jj] == x1;
+        uint64_t mm = __ballot(mine);
+        if (mine) L.hactor[jj] = 0;
+        if (lane == 0) {
+          while (mm) {
+            const uint32_t k = d0 + (uint32_t)__builtin_ctzll(mm);
+            mm &= mm - 1;
+            const Desc& e = a.slots[L.slot[k]].d;  // written by this workgroup this pass
+            if (!ok || e.seq != next) {
+              ok = false;
+              continue;
+            }
+            st = (st * 1000003ull) ^ e.p.h.x;
+            L.hx[k] = st;
+            L.hidx[nh++] = (uint16_t)k;
+            L.nt[k] = 0;
+            ++next;
+            any = true;
+          }
+        }
+      }
+      if (lane == 0 && any) {
+        st_dev(&act->state, st);
+        st_dev_rel(&act->seq_done, next);
+      }
     }
   }
-  L.nh = nh;
+  if (lane == 0) L.nh = nh;
 }
 
 // The replies of the entries run by run_hash_entries_locked: one completion
@@ -695,8 +714,8 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
       if (t == 0) unlock_drain(a);
       return false;
     }
+    if (t < 64) run_hash_entries_locked(a, L, 1);
     if (t == 0) {
-      run_hash_entries_locked(a, L, 1);
       L.pos[0] = 0;
       L.scan[0] = 0;
     }
@@ -719,7 +738,7 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
         return false;
       }
     }
-    if (t == 0) run_hash_entries_locked(a, L, cnt);
+    if (t < 64) run_hash_entries_locked(a, L, cnt);
     __syncthreads();
     // Grouping: stable counting sort of the batch by key.
     if (a.grouping == CAF_GROUP_LPT) {

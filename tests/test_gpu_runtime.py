@@ -51,19 +51,20 @@ def test_fifo_hash_chain_three_senders(sysm):
 
 
 def test_hash_chains_interleaved_with_sends_and_echo(sysm):
-    """Two stateful actors whose messages are interleaved in the mailbox
+    """Five stateful actors whose messages are interleaved in the mailbox
     with sends (no reply) and echo requests: each actor's state follows its
     own messages in mailbox order (Sec. 2: one mailbox per actor, FIFO), so
-    a drain pass holding entries of both applies each chain in order."""
+    a drain pass holding entries of several applies each chain in order."""
     from paper_1505_07368_amd import binding as cg
-    acts = [sysm.spawn(cg.BHV_HASHCHAIN), sysm.spawn(cg.BHV_HASHCHAIN)]
+    nact = 5
+    acts = [sysm.spawn(cg.BHV_HASHCHAIN) for _ in range(nact)]
     e = sysm.spawn(cg.BHV_NOOP)
     g = gen.rng(9)
-    state = [0, 0]
+    state = [0] * nact
     checks, echoes = [], []
-    for i in range(600):
-        k = int(g.integers(0, 3))
-        if k == 2:
+    for i in range(900):
+        k = int(g.integers(0, nact + 1))
+        if k == nact:
             x = np.array([i], np.int32)
             echoes.append((i, sysm.request(e, inputs=[x])))
             continue
@@ -80,7 +81,7 @@ def test_hash_chains_interleaved_with_sends_and_echo(sysm):
         st, v = f.result()
         assert st == cg.OK and int(v[0]) == i
     # the chains continue from the state the sends advanced
-    for k in range(2):
+    for k in range(nact):
         st, v = sysm.request(acts[k], cg.caf_hash_args(7)).result()
         assert st == cg.OK and int(v[0]) == oracle.hash_step(state[k], 7)
 
