@@ -235,10 +235,13 @@ void caf_future_release(caf_future* fut);
  * completes normally. */
 int caf_gpu_quit(caf_gpu_system* sys, caf_actor actor, uint32_t exit_reason);
 
-/* become (Sec. 6): the actor's behaviour, signature and spawn arguments
- * change for every message submitted after this call; messages submitted
- * before it are still handled by the old behaviour (each carries its
- * behaviour through the mailbox), so the swap takes effect in mailbox order.
+/* become (Sec. 5.3, function-based actors; Sec. 5.4, class-based actors):
+ * the actor's behaviour, signature and spawn arguments change for every
+ * message submitted after this call; messages submitted before it are still
+ * handled by the old behaviour (each carries its behaviour through the
+ * mailbox), so the swap takes effect in mailbox order.  This is the
+ * dynamically typed actor's become: the new behaviour may have another
+ * signature (a statically typed actor would have to keep its interface).
  * The actor's device-resident state and the order in which its stateful
  * messages update it carry over.  CAF_E_NO_ACTOR for an unknown or quit
  * actor; CAF_E_INVALID for an unknown behaviour, forward target or palette

@@ -146,10 +146,11 @@ int caf_ref_timeout(ref_system* sys, uint64_t req);
 uint64_t caf_ref_dequeue_log(ref_system* sys, uint64_t actor, uint32_t* senders, uint32_t* seqs,
                              uint64_t cap);
 uint64_t caf_ref_actor_state(ref_system* sys, uint64_t actor);
-/* become (Sec. 6): the actor's behaviour and signature change for every
- * message enqueued after this call; earlier ones still meet the old
- * behaviour (the change travels through the mailbox as a control entry, in
- * order).  The actor's state is kept.  REF_E_NO_ACTOR for an unknown or
+/* become (Sec. 5.3, function-based actors; Sec. 5.4, class-based actors):
+ * the actor's behaviour and signature change for every message enqueued
+ * after this call (a dynamically typed actor's become); earlier ones still
+ * meet the old behaviour (the change travels through the mailbox as a
+ * control entry, in order).  The actor's state is kept.  REF_E_NO_ACTOR for an unknown or
  * quit actor, REF_E_INVALID for a bad behaviour or forward target. */
 int caf_ref_become(ref_system* sys, uint64_t actor, int32_t behavior, const ref_spawn_args* args);
 

@@ -284,6 +284,10 @@ __device__ __forceinline__ void hash_step(KArgsC& a, const Desc& d) {
   uint64_t* io = reinterpret_cast<uint64_t*>(a.slots[d.slot].inline_out);
   io[0] = s;
   io[1] = 0;
+  // A reply that does not travel in the completion record goes to the
+  // message's output buffer (a caller-owned one, or the arena's); the
+  // completion that follows releases it.
+  if (!(d.flags & DF_INLINE_OUT) && d.out) *reinterpret_cast<uint64_t*>(d.out) = s;
   st_dev_rel(&act->seq_done, d.seq + 1u);
 }
 

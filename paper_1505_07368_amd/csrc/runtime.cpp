@@ -103,6 +103,7 @@ class Arena {
     quick_[sz].push_back(addr - base_);
     if (++quick_blocks_ > kQuickMax) flush_quick();
   }
+  uint64_t size() const { return size_; }
   uint64_t in_use() const { return in_use_; }
   uint64_t peak() const { return peak_; }
 
@@ -288,6 +289,8 @@ struct caf_gpu_system {
   uint32_t gemm_tile = 0;
   uint32_t grid_full = 0, grid_light = 0;  // drain-kernel workgroups per variant
   std::atomic<bool> need_full{false};       // a GEMM actor exists
+  bool last_full = false;                   // variant of the latest drain launch (launch_mu)
+  hipEvent_t handover = nullptr;            // light -> full launch ordering (launch_mu)
   std::map<PlainShape, PlainGraph> graphs;  // CAF_MODE_PLAIN_GRAPH, guarded by mu
   // CPU actors of the CPU+GPU split (offload.cpp)
   cafgpu::CpuPool* cpu_pool = nullptr;
@@ -423,6 +426,16 @@ void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
   // The previous launch may still be finishing its last tiles on the other
   // stream; launches cooperate through the shared counters.
   hipStream_t st = s->dstream[a.gen & 1u];
+  // A light launch cannot run GEMM tiles, and its workgroups may still
+  // reserve tile indices until they notice that their launch retires.  The
+  // first full launch after light ones therefore starts only once every
+  // earlier launch has exited: it waits for the other drain stream (and its
+  // own stream orders it after the launch before that), so no light
+  // workgroup is resident when a product's tiles are published.
+  if (a.full && !s->last_full && a.gen > 1) {
+    hipEventRecord(s->handover, s->dstream[(a.gen + 1) & 1u]);
+    hipStreamWaitEvent(st, s->handover, 0);
+  }
   const bool timed = s->ev_used < s->ev_pool.size();
   if (timed) hipEventRecord(s->ev_pool[s->ev_used].first, st);
   const hipError_t e = launch_drain(a, st);
@@ -431,6 +444,7 @@ void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
     return;
   }
   if (timed) hipEventRecord(s->ev_pool[s->ev_used++].second, st);
+  s->last_full = a.full != 0;
   s->launched_gen.store(a.gen, std::memory_order_release);
   s->st_drain_launches++;
 }
@@ -776,6 +790,24 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
     d.hop_actor[h] = ((uint32_t)hbeh[h] << 16) | (hidx[h] + 1);
 
   // ---- admission: a slot plus every arena buffer the message needs ------
+  // A message whose buffers together exceed the whole arena can never be
+  // admitted: refused at once, also in blocking mode (waiting would never end).
+  {
+    uint64_t need = 0;
+    for (uint32_t i = 0; i < n_in; ++i)
+      if (!in[i].on_device && !(inline_in && i == 0))
+        need += Arena::granules(in[i].numel * dtype_bytes(in[i].dtype));
+    for (uint32_t k = 0; k <= nhops; ++k) {
+      const Shape& shk = k == 0 ? sh : hsh[k - 1];
+      if (k == nhops && (inline_out || user_out)) continue;
+      const uint64_t bytes = shk.numel * dtype_bytes(shk.dtype);
+      need += Arena::granules(bytes ? bytes : 4);
+    }
+    if (need > s->arena.size()) {
+      s->st_rejected++;
+      return CAF_E_OVERLOAD;
+    }
+  }
   Block staged[2];
   Block sout[1 + kMaxHops];
   uint32_t slot = 0;
@@ -1031,6 +1063,7 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   }
   chk(hipStreamCreateWithFlags(&s->dstream[1], hipStreamNonBlocking));
   s->own_dstream[1] = true;
+  chk(hipEventCreateWithFlags(&s->handover, hipEventDisableTiming));
   const unsigned hflags = hipHostMallocCoherent | hipHostMallocMapped;
   chk(hipHostMalloc((void**)&s->hctl, sizeof(HostCtl), hflags));
   chk(hipHostMalloc((void**)&s->hring, sizeof(Desc) * cap, hflags));
@@ -1340,6 +1373,7 @@ int caf_gpu_shutdown(caf_gpu_system* s) {
     hipEventDestroy(e.first);
     hipEventDestroy(e.second);
   }
+  if (s->handover) hipEventDestroy(s->handover);
   for (auto& kv : s->graphs) {
     hipGraphExecDestroy(kv.second.exec);
     hipGraphDestroy(kv.second.graph);

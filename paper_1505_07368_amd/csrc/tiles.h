@@ -56,64 +56,99 @@ __device__ inline uint32_t wave_id() { return threadIdx.x >> 6; }
 // empty -- the early exit is wave-uniform and no lane's count moves past
 // its escape.
 // ---------------------------------------------------------------------------
-// Escape counts of two pixels per lane, interleaved, so each wave carries
-// two dependency chains (in float and in double) and the vector units stay
-// fed at five waves per SIMD.  The lanes still iterating are wave-wide
-// ballot masks held in scalar registers.  Lanes that escaped keep computing
-// (their values no longer matter), so the common path is the arithmetic of
-// one iteration per pixel plus scalar bookkeeping; a pixel's count is frozen
-// at its first escape (a rare branch), and the wave leaves as soon as both
-// masks are empty.  valid = false marks a lane's pixel as outside the tile.
+// Escape counts of P pixels per lane, interleaved, so each wave carries P
+// independent dependency chains.  gfx950 issues two plain fp32 VALU
+// instructions per SIMD in one quad cycle when two waves have one ready, so
+// the loop is written to keep the vector units fed and the scalar unit (one
+// per compute unit, shared by its four SIMDs) idle:
+//  * a pixel that escapes is frozen by making its zr a quiet NaN: |z|^2 is
+//    then NaN, which never passes the > 4 test again, and lanes outside the
+//    tile start frozen (cr = NaN).  The per-iteration test therefore needs
+//    no live-lane masking: it is one compare of the largest of the P
+//    magnitudes against 4 -- the maximum ignores NaN operands and returns
+//    one of the others exactly, so the test is exactly "some live pixel
+//    escapes" -- and one branch on its result;
+//  * the iteration limit is checked once per block of kEscapeUnroll
+//    iterations; an escape seen at an iteration >= max_iter (the last block
+//    may run past it) leaves the count at max_iter;
+//  * counts, freezing and the check for a finished wave are selects on the
+//    rare branch, which ends the loop at the end of the current block once
+//    every pixel of the wave has escaped.
+// Each iteration is the recurrence's 3 multiplies and 5 adds/subtracts per
+// pixel, in the order the oracle takes them, and each pixel's test is
+// decided by its own |z|^2 > 4.  valid[p] = false marks a lane's pixel p as
+// outside the tile.
+constexpr uint32_t kEscapeUnroll = 4;
+
+// The larger of two magnitudes (v_max): IEEE maxNum, so a NaN operand (a
+// frozen pixel) yields the other operand, and otherwise one of the two
+// operands exactly.
+__device__ __forceinline__ float max_of(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double max_of(double a, double b) { return __builtin_fmax(a, b); }
 template <typename T>
-__device__ __forceinline__ void escape_count2(T cr0, T ci0, T cr1, T ci1, uint32_t max_iter,
-                                              bool v0, bool v1, uint32_t& n0, uint32_t& n1) {
-  uint64_t l0 = __builtin_amdgcn_ballot_w64(v0);
-  uint64_t l1 = __builtin_amdgcn_ballot_w64(v1);
+__device__ __forceinline__ T quiet_nan() {
+  if constexpr (sizeof(T) == 4) return __builtin_nanf("");
+  else return __builtin_nan("");
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void escape_count(const T (&cr_in)[P], const T (&ci_in)[P],
+                                             const bool (&valid)[P], uint32_t max_iter,
+                                             uint32_t (&n)[P]) {
   const uint32_t lim = __builtin_amdgcn_readfirstlane(max_iter);
-  n0 = lim;
-  n1 = lim;
-  T ar = T(0), ai = T(0), br = T(0), bi = T(0);
-  uint32_t it = 0;
-  if (lim == 0 || (l0 | l1) == 0) return;
-  // One iteration of both pixels; false once the wave is done.
-  auto step = [&]() __attribute__((always_inline)) -> bool {
-    T ar2 = ar * ar;
-    T ai2 = ai * ai;
-    T am = ar2 + ai2;
-    T br2 = br * br;
-    T bi2 = bi * bi;
-    T bm = br2 + bi2;
-    const bool e0 = am > T(4), e1 = bm > T(4);
-    const uint64_t E0 = __builtin_amdgcn_ballot_w64(e0) & l0;
-    const uint64_t E1 = __builtin_amdgcn_ballot_w64(e1) & l1;
-    if (__builtin_expect((E0 | E1) != 0, 0)) {
-      asm volatile("" ::: "memory");
-      if (e0 && n0 == lim) n0 = it;
-      if (e1 && n1 == lim) n1 = it;
-      l0 &= ~E0;
-      l1 &= ~E1;
+  const T nan = quiet_nan<T>();
+  T zr[P], zi[P], cr[P], ci[P];
+  uint32_t left = 0;  // this lane's pixels still iterating
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    n[p] = lim;
+    cr[p] = valid[p] ? cr_in[p] : nan;
+    ci[p] = ci_in[p];
+    zr[p] = T(0);
+    zi[p] = T(0);
+    left += valid[p] ? 1u : 0u;
+  }
+  if (lim == 0 || __builtin_amdgcn_ballot_w64(left != 0) == 0) return;
+  uint32_t stop = lim;  // lowered on the rare branch once the wave is done
+  for (uint32_t it = 0; it < stop; it += kEscapeUnroll) {
+#pragma unroll
+    for (uint32_t u = 0; u < kEscapeUnroll; ++u) {
+      T m[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const T r2 = zr[p] * zr[p];
+        const T i2 = zi[p] * zi[p];
+        m[p] = r2 + i2;
+        const T t = zr[p] * zi[p];
+        const T tt = t + t;
+        zi[p] = tt + ci[p];
+        const T d = r2 - i2;
+        zr[p] = d + cr[p];
+      }
+      T mx = m[0];
+#pragma unroll
+      for (int p = 1; p < P; ++p) mx = max_of(mx, m[p]);
+      if (__builtin_expect(__builtin_amdgcn_ballot_w64(mx > T(4)) != 0, 0)) {
+        asm volatile("" ::: "memory");
+        const uint32_t k = it + u;
+        const uint32_t kk = k < lim ? k : lim;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const bool e = m[p] > T(4);
+          n[p] = e ? kk : n[p];
+          zr[p] = e ? nan : zr[p];
+          left -= e ? 1u : 0u;
+        }
+        if (__builtin_amdgcn_ballot_w64(left != 0) == 0) stop = 0;
+      }
     }
-    T at = ar * ai;
-    T att = at + at;
-    ai = att + ci0;
-    T ad = ar2 - ai2;
-    ar = ad + cr0;
-    T bt = br * bi;
-    T btt = bt + bt;
-    bi = btt + ci1;
-    T bd = br2 - bi2;
-    br = bd + cr1;
-    ++it;
-    return it != lim && (l0 | l1) != 0;
-  };
-  // Two iterations per loop trip: the values of one iteration feed the next
-  // in alternating registers, without copies at the back edge.
-  while (step() && step()) {
   }
 }
 
 template <typename T>
 __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
+  // pixels per lane: four in float (the loop dual-issues), two in double
+  constexpr int P = sizeof(T) == 4 ? 4 : 2;
   T re_min, im_min, step_re, step_im;
   if constexpr (sizeof(T) == 8) {
     re_min = d.p.m64.re_min;
@@ -142,17 +177,17 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) *lds_ctr = 0;
   __syncthreads();
-  // A wave takes two blocks at a time.
+  // A wave takes P blocks at a time, one pixel of each per lane.
   for (;;) {
     uint32_t b = 0;
-    if (lane == 0) b = atomicAdd(lds_ctr, 2u);
+    if (lane == 0) b = atomicAdd(lds_ctr, (uint32_t)P);
     b = __builtin_amdgcn_readfirstlane(b) + b0;
     if (b >= b1) break;
-    uint32_t y[2], x[2];
-    bool v[2];
-    T cr[2], ci[2];
+    uint32_t y[P], x[P], n[P];
+    bool v[P];
+    T cr[P], ci[P];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < P; ++k) {
       const uint32_t bk = b + k;
       const uint32_t by = bk / bw, bx = bk - by * bw;
       y[k] = by * kMandelBlockH + lane / kMandelBlockW;
@@ -165,10 +200,9 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
       T ym = gy * step_im;
       ci[k] = im_min + ym;
     }
-    uint32_t n[2];
-    escape_count2<T>(cr[0], ci[0], cr[1], ci[1], max_iter, v[0], v[1], n[0], n[1]);
+    escape_count<T, P>(cr, ci, v, max_iter, n);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < P; ++k) {
       if (!v[k]) continue;
       const uint64_t at = (uint64_t)y[k] * width + x[k];
       if (rgba) out32[at] = pal[min(n[k], pal_last)];

@@ -282,6 +282,80 @@ def test_become_gemm_while_a_light_launch_runs():
         assert rel_fro(C.cpu().numpy().reshape(64, 64), oracle.gemm(A, B)) <= 1e-5
 
 
+def test_become_gemm_multi_tile_products_during_light_launch():
+    """Multi-tile products (n = 256 at 64-wide tiles: 16 tiles each) sent
+    while a light drain launch (no matrix tiles) is busy with Mandelbrot
+    tiles: the first full launch starts only after every light workgroup has
+    left, so no product tile is claimed by a light workgroup (which would
+    fail it).  Every product and every Mandelbrot reply against the oracle."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode="batched", arena_bytes=256 << 20, ring_slots=256, gemm_tile=64,
+                   idle_exit_us=200000) as s:
+        e = s.spawn(cg.BHV_NOOP)
+        m = s.spawn(cg.BHV_MANDELBROT)
+        vp = gen.tiny_viewport()
+        first = [s.request(m, cg.mandel_args(vp, row0=r0, rows=64)) for r0 in range(0, 512, 64)]
+        first.append(s.request(m, slow_mandel_args(cg, rows=128)))
+        assert s.become(e, cg.BHV_GEMM) == cg.OK
+        n = 256
+        pairs = [gen.gemm_pair(300 + k, n) for k in range(8)]
+        dev = [(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()) for A, B in pairs]
+        torch.cuda.synchronize()
+        gf = [s.request(e, cg.caf_gemm_args(n, cg.F32), inputs=[At, Bt]) for At, Bt in dev]
+        later = [s.request(m, cg.mandel_args(vp, row0=r0, rows=64)) for r0 in range(0, 512, 64)]
+        for k, f in enumerate(gf):
+            st, C = f.result()
+            assert st == cg.OK, (k, st)
+            A, B = pairs[k]
+            assert rel_fro(C.cpu().numpy().reshape(n, n), oracle.gemm(A, B)) <= 1e-5, k
+        ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, 512, 0, 512, 100)
+        for fs in (first[:8], later):
+            for r0, f in zip(range(0, 512, 64), fs):
+                st, img = f.result()
+                assert st == cg.OK
+                assert (img.cpu().numpy().reshape(64, 512) == ref[r0:r0 + 64]).all(), r0
+        st, _ = first[8].result()
+        assert st == cg.OK
+
+
+def test_hash_reply_into_caller_buffer(sysm):
+    """A hash-chain request with a caller-owned device output buffer: the
+    new state is written there (the request goes the tile way, since its
+    reply does not travel in the completion record), in every form."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    a = sysm.spawn(cg.BHV_HASHCHAIN)
+    xs = [int(v) for v in gen.rng(17).integers(0, 2 ** 62, size=12)]
+    outs = [torch.zeros(1, dtype=torch.uint64, device="cuda") for _ in xs]
+    torch.cuda.synchronize()
+    futs = [sysm.request(a, cg.caf_hash_args(x), out=o) for x, o in zip(xs, outs)]
+    state = 0
+    for x, f, o in zip(xs, futs, outs):
+        state = oracle.hash_step(state, x)
+        st, v = f.result()
+        assert st == cg.OK and v is None
+        got = int(o.view(torch.int64).cpu().item()) & (2 ** 64 - 1)
+        assert got == state, (got, state)
+
+
+def test_blocking_request_larger_than_arena_is_refused():
+    """In blocking mode a request whose buffers can never fit the arena is
+    refused at once (it would otherwise wait forever)."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode="batched", arena_bytes=1 << 20, blocking=True) as s:
+        g = s.spawn(cg.BHV_GEMM)
+        n = 1024  # a 4 MiB reply into a 1 MiB arena
+        A = torch.zeros(n * n, device="cuda")
+        rc, f = s.request_raw(g, cg.caf_gemm_args(n, cg.F32), inputs=[A, A])
+        assert rc == cg.E_OVERLOAD and f is None
+        m = s.spawn(cg.BHV_MANDELBROT)
+        st, img = s.request(m, cg.caf_mandel_args(-2, -1, 0.1, 0.1, 8, 8, 0, 8, 10,
+                                                  cg.F32)).result()
+        assert st == cg.OK and img.numel() == 64
+
+
 def test_batched_pingpong_keeps_its_launch():
     """Window-1 ping-pong in batched mode (default 50 us linger): the drain
     launch stays up between requests instead of retiring in every gap (a

@@ -2,28 +2,45 @@
 
 Each test runs a workload the benchmark times, through the same entry points
 and the same System configuration (delivery mode, ring, work-tile size and
-grid candidates of the autotuner), and checks sampled outputs against the
-oracle one by one, plus properties that hold for every output:
+grid candidates of the autotuner), and compares the outputs with the oracle:
 
   * the headline image batch: 8 boundary viewports of 1920x1080 at max_iter
-    1000, 17 row-tile messages each (the last has 56 rows), fp32 and fp64;
+    1000, 17 row-tile messages each (the last has 56 rows), fp32 and fp64:
+    every pixel of every image against the oracle, and the escape-count sums
+    against the oracle's stored sums (tests/golden/headline_sums.json);
   * the grouped GEMM batch: n drawn from {64, 128, 256, 512}, fp32 and bf16,
     both output-tile edges;
   * the serving mix: Mandelbrot squares 64^2..512^2 at max_iter 256..4096 and
-    fp32 GEMMs n = 32..512 through the non-blocking persistent system;
-  * the GEMM leg's 4096-request batch and the pipeline leg's 100,000 chains
-    as the benchmark runs them.
+    fp32 GEMMs n = 32..512 through the non-blocking persistent system, every
+    reply compared in full;
+  * the GEMM leg's 4096-request batch (every 64th product against the
+    oracle) and the pipeline leg's 100,000 chains as the benchmark runs them.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_1505_07368_amd import gen
+from tests import oracle_par
 from tests.gpu_util import rel_fro
 
 pytestmark = pytest.mark.gpu
 
 SEEDS = list(range(8))
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "headline_sums.json")))
+
+_ORACLE_IMAGES = {}
+
+
+def oracle_images(fp):
+    """The oracle's eight headline images (computed once per session)."""
+    if fp not in _ORACLE_IMAGES:
+        _ORACLE_IMAGES[fp] = oracle_par.mandel_images([gen.boundary_viewport(sd) for sd in SEEDS],
+                                                      fp)
+    return _ORACLE_IMAGES[fp]
 
 
 def _image_batch(cg, torch, s, fp):
@@ -45,15 +62,18 @@ def _image_batch(cg, torch, s, fp):
 
 
 def _check_images(imgs, fp):
-    for seed, (vp, img) in zip(SEEDS, imgs):
+    """Every pixel of every image against the oracle, and the sums against
+    the oracle's stored sums."""
+    refs = oracle_images(fp)
+    total = 0
+    for seed, (vp, img), ref in zip(SEEDS, imgs, refs):
         host = img.cpu().numpy().reshape(vp.height, vp.width)
-        assert host.min() >= 1 and host.max() <= vp.max_iter
-        g = gen.rng(500 + seed)
-        rows = set(g.integers(0, vp.height, size=2).tolist()) | {0, 63, 64, 1023, 1024, 1079}
-        for y in sorted(rows):
-            ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, y,
-                                    1, vp.max_iter, fp)
-            assert (host[y] == ref[0]).all(), (seed, y, int((host[y] != ref[0]).sum()))
+        bad = host != ref
+        assert not bad.any(), (seed, int(bad.sum()), np.argwhere(bad)[:4].tolist())
+        s = int(host.sum(dtype=np.int64))
+        assert s == GOLDEN[fp]["images"][seed]["sum"], (seed, s)
+        total += s
+    assert total == GOLDEN[fp]["total"]
 
 
 @pytest.mark.parametrize("px,half_grid", [(512, False), (1024, False), (2048, False),
@@ -134,15 +154,16 @@ def test_gemm_batch_sampled(dtype, te):
     assert seen == {64, 128, 256, 512}
 
 
-def test_serving_mix_sampled():
-    """Serving-mix messages (closed loop, same system configuration as the
-    serving benchmark); sampled rows of each Mandelbrot square and whole
-    GEMMs against the oracle."""
+def test_serving_mix_full():
+    """Every request of a 0.1 s serving-mix run at 1e4 arrivals/s (about
+    1,000 messages, issued as one burst through the same system
+    configuration as the serving benchmark): every Mandelbrot square
+    compared pixel for pixel, every GEMM in full (relative Frobenius error)."""
     import torch
     from paper_1505_07368_amd import binding as cg
-    d = gen.serving_mix_arrays(0, 1e4, 0.006)
+    d = gen.serving_mix_arrays(0, 1e4, 0.1)
     cnt = d["arrival_ns"].size
-    assert cnt >= 30
+    assert cnt >= 900
     s = cg.System(mode="persistent", arena_bytes=32 << 30, ring_slots=8192, blocking=False)
     try:
         m = s.spawn(cg.BHV_MANDELBROT)
@@ -163,35 +184,45 @@ def test_serving_mix_sampled():
                 C = torch.full((n * n,), float("nan"), device="cuda")
                 msgs.append({"actor": gm, "args": cg.caf_gemm_args(n, cg.F32),
                              "inputs": [At, Bt], "out": C})
-                cases.append(("gemm", (A, B, At, Bt), C))
+                cases.append(("gemm", (A, B), C))
         torch.cuda.synchronize()
         rc, _, st, _ = s.drive(msgs, window=len(msgs))
         assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
     finally:
         s.shutdown()
-    g = gen.rng(9)
-    for kind, x, out in cases:
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.lib()
+
+    def ref_of(case):
+        kind, x, _ = case
+        if kind == "mandel":
+            vp = x
+            return oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width, 0,
+                                     vp.height, vp.max_iter, "f32")
+        return oracle.gemm(x[0], x[1])
+
+    with ThreadPoolExecutor(oracle_par.threads()) as ex:
+        refs = list(ex.map(ref_of, cases))
+    nm = 0
+    for (kind, x, out), ref in zip(cases, refs):
         if kind == "mandel":
             vp = x
             host = out.cpu().numpy().reshape(vp.height, vp.width)
-            assert host.min() >= 1 and host.max() <= vp.max_iter
-            for y in sorted({0, vp.height - 1, int(g.integers(0, vp.height))}):
-                ref = oracle.mandelbrot(vp.re_min, vp.im_min, vp.step_re, vp.step_im, vp.width,
-                                        y, 1, vp.max_iter, "f32")
-                assert (host[y] == ref[0]).all(), (vp, y)
+            assert (host == ref).all(), (vp, int((host != ref).sum()))
+            nm += 1
         else:
-            A, B = x[0], x[1]
-            n = A.shape[0]
-            err = rel_fro(out.cpu().numpy().reshape(n, n), oracle.gemm(A, B))
+            n = x[0].shape[0]
+            err = rel_fro(out.cpu().numpy().reshape(n, n), ref)
             assert err <= 1e-5, (n, err)
+    assert nm >= 600
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_gemm_bench_batch_full_size(dtype):
     """The benchmark's GEMM leg as timed: 4096 requests, n ~ U{64..512},
     inputs drawn on the device, batched drain with max_batch 1024.  Every
-    output is checked finite; one message of each size against the oracle
-    (inputs copied back)."""
+    output is checked finite; every 64th product (and one of each size)
+    against the oracle (inputs copied back)."""
     import torch
     from paper_1505_07368_amd import binding as cg
     count = 4096
@@ -238,17 +269,24 @@ def test_gemm_bench_batch_full_size(dtype):
     finally:
         s.shutdown()
     assert torch.isfinite(C).all()
-    for size in (64, 128, 256, 512):
-        i = int(np.nonzero(sizes == size)[0][0])
-        o, m = int(offs[i]), size * size
+    picks = list(range(0, count, 64))
+    for size in (64, 128, 256, 512):  # and at least one product of every size
+        picks.append(int(np.nonzero(sizes == size)[0][0]))
+    pairs, outs = [], []
+    for i in sorted(set(picks)):
+        size, o = int(sizes[i]), int(offs[i])
+        m = size * size
         if dtype == "bf16":
             Ah = A[o:o + m].view(torch.int16).cpu().numpy().view(np.uint16).reshape(size, size)
             Bh = B[o:o + m].view(torch.int16).cpu().numpy().view(np.uint16).reshape(size, size)
         else:
             Ah = A[o:o + m].cpu().numpy().reshape(size, size)
             Bh = B[o:o + m].cpu().numpy().reshape(size, size)
-        err = rel_fro(C[o:o + m].cpu().numpy().reshape(size, size), oracle.gemm(Ah, Bh, dtype))
-        assert err <= 1e-5, (size, err)
+        pairs.append((Ah, Bh))
+        outs.append((i, C[o:o + m].cpu().numpy().reshape(size, size)))
+    for (i, got), ref in zip(outs, oracle_par.gemms(pairs, dtype)):
+        err = rel_fro(got, ref)
+        assert err <= 1e-5, (i, got.shape[0], err)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
