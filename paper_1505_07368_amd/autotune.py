@@ -24,7 +24,10 @@ from . import binding as cg
 
 
 def _device_name(torch) -> str:
-    return torch.cuda.get_device_name(0)
+    # the device and the kernel sources: a cache written for other kernels
+    # is not reused
+    from . import profsum
+    return f"{torch.cuda.get_device_name(0)}|src:{profsum.source_digest()[:16]}"
 
 
 def _load_cache(path):

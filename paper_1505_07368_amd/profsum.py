@@ -111,6 +111,15 @@ def main(argv=None):
     ap.add_argument("--pmc-last", type=int, default=0)
     ap.add_argument("--mfma", help="--pmc csv with SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE, "
                     "SQ_INSTS_VALU_MFMA_MOPS_*")
+    ap.add_argument("--counters", action="append", default=[],
+                    help="--pmc csv of any counters: their per-dispatch means are listed")
+    ap.add_argument("--iters", type=float, default=0.0,
+                    help="algorithmic escape-time iterations per dispatch: the instruction "
+                    "counters are also given per iteration, and SQ_INSTS_VALU as lane "
+                    "operations per second over the mean dispatch duration")
+    ap.add_argument("--ops-per-iter", type=float, default=9.0)
+    ap.add_argument("--valu-peak", type=float, default=0.0,
+                    help="VALU lane operations per second of the chip, for the fractions")
     ap.add_argument("--xcc", type=int, default=8)
     ap.add_argument("--simds", type=int, default=1024)
     ap.add_argument("--note", action="append", default=[])
@@ -157,6 +166,50 @@ def main(argv=None):
         lines += [f"| {d['dispatch']} | {100 * d['util']:.1f}% | {d['flops'] / 1e9:.2f} |"
                   for d in md]
         lines += [""]
+    if a.counters:
+        means = {}
+        for path in a.counters:
+            by = {}
+            for r in _rows(path):
+                if a.kernel in r["Kernel_Name"]:
+                    by.setdefault(r["Counter_Name"], {})[int(r["Dispatch_Id"])] = \
+                        float(r["Counter_Value"])
+            for name, per in by.items():
+                vals = [per[k] for k in sorted(per)]
+                vals = vals[-a.pmc_last:] if a.pmc_last else vals
+                means[name] = _mean(vals)
+        per_iter = a.iters > 0
+        lines += ["Counters, mean per dispatch" + (" (instruction counts are wave "
+                  "instructions; per iteration = / the dispatch's algorithmic iterations)"
+                  if per_iter else "") + ":", "",
+                  "| counter | per dispatch |" + (" per iteration |" if per_iter else ""),
+                  "|---|---|" + ("---|" if per_iter else "")]
+        for name in sorted(means):
+            row = f"| {name} | {means[name]:.6g} |"
+            if per_iter:
+                row += f" {means[name] / a.iters:.4f} |" if name.startswith("SQ_INSTS") else " |"
+            lines.append(row)
+        lines.append("")
+        for name, v in means.items():
+            kv[f"pmc_{name}"] = f"{v:.6g}"
+        if per_iter and "SQ_INSTS_VALU" in means:
+            t = _mean(sel) * 1e-9
+            lane_ops = means["SQ_INSTS_VALU"] * 64.0
+            alg = a.iters * a.ops_per_iter
+            lines += [f"- Executed VALU lane operations per dispatch (SQ_INSTS_VALU x 64): "
+                      f"{lane_ops:.4g}, {lane_ops / t / 1e12:.2f}e12 per second over the "
+                      f"mean dispatch; algorithmic ({a.ops_per_iter:g} per iteration): "
+                      f"{alg:.4g}, {alg / t / 1e12:.2f}e12 per second; executed / "
+                      f"algorithmic = {lane_ops / alg:.4f}."]
+            kv.update({"iters_per_dispatch": f"{a.iters:.0f}",
+                       "valu_lane_ops_per_s": f"{lane_ops / t:.6g}",
+                       "alg_ops_per_s": f"{alg / t:.6g}"})
+            if a.valu_peak:
+                lines += [f"- Against {a.valu_peak / 1e12:.2f}e12 lane operations per second: "
+                          f"executed {lane_ops / t / a.valu_peak:.4f}, algorithmic "
+                          f"{alg / t / a.valu_peak:.4f}."]
+                kv["alg_frac"] = f"{alg / t / a.valu_peak:.4f}"
+            lines.append("")
     lines += [f"- {n}" for n in a.note] + ([""] if a.note else [])
     lines += ["Machine-readable:", ""] + [f"- {k}: {v}" for k, v in kv.items()]
     print("\n".join(lines))
