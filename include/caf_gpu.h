@@ -348,6 +348,32 @@ int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor, const caf_mande
                        uint32_t gpu_rows, uint32_t cpu_threads, uint16_t* dev_stage,
                        uint16_t* out_host, caf_offload_times* times);
 
+/* caf_offload_mandel_noalloc: for callers that cannot allocate (code that
+ * must not call hipMalloc, harnesses that forbid it, tight serving loops).
+ * The same split as caf_offload_mandel, with the same results, except that
+ * the GPU share is staged in the library's own device array instead of a
+ * caller's dev_stage: a fixed CAF_OFFLOAD_NOALLOC_STAGE_BYTES array per
+ * device, held from the first caf_gpu_init on that device until the
+ * process ends.  The call allocates no device or pinned host memory (no
+ * hipMalloc, hipHostMalloc or hipFree, no arena bytes: the replies go to
+ * the array) and keeps its request table on the stack.
+ * Limits: gpu_rows * width * 2 <= CAF_OFFLOAD_NOALLOC_STAGE_BYTES and
+ * gpu_rows <= CAF_OFFLOAD_NOALLOC_MAX_ROWS, else CAF_E_INVALID; a CPU share
+ * (gpu_rows < height) needs the system's CPU actors to be running with
+ * cpu_threads workers already (an earlier caf_offload_mandel call with the
+ * same cpu_threads starts them), else CAF_E_INVALID, since starting threads
+ * allocates.  Every call on one device shares that device's array and
+ * leaves its GPU share there: calls on one system run one at a time, but
+ * calls from two systems on the same device that overlap race on the
+ * array.  Other errors as caf_offload_mandel; CAF_E_DEVICE if the array's
+ * address could not be found. */
+#define CAF_OFFLOAD_NOALLOC_STAGE_BYTES (16u << 20)
+#define CAF_OFFLOAD_NOALLOC_MAX_ROWS 16384u
+int caf_offload_mandel_noalloc(caf_gpu_system* sys, caf_actor gpu_actor,
+                               const caf_mandel_args* image, uint32_t gpu_rows,
+                               uint32_t cpu_threads, uint16_t* out_host,
+                               caf_offload_times* times);
+
 #ifdef __cplusplus
 }
 #endif

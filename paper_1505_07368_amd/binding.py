@@ -29,7 +29,11 @@ EXPORTED = ["caf_gpu_init", "caf_gpu_spawn", "caf_gpu_send", "caf_gpu_request",
             "caf_future_wait", "caf_future_poll", "caf_future_id", "caf_future_release",
             "caf_gpu_quit", "caf_gpu_drain", "caf_gpu_shutdown", "caf_gpu_strerror",
             "caf_gpu_get_stats", "caf_gpu_drain_kernel_ms", "caf_gpu_drive",
-            "caf_cpu_mandel_rows", "caf_offload_mandel", "caf_gpu_become"]
+            "caf_cpu_mandel_rows", "caf_offload_mandel", "caf_gpu_become",
+            "caf_offload_mandel_noalloc"]
+# limits of caf_offload_mandel_noalloc (caf_gpu.h)
+OFFLOAD_NOALLOC_STAGE_BYTES = 16 << 20
+OFFLOAD_NOALLOC_MAX_ROWS = 16384
 
 
 class caf_buf(C.Structure):
@@ -123,6 +127,8 @@ def load():
         "caf_gpu_become": ([vp, u64, i32, P(caf_spawn_args)], C.c_int),
         "caf_offload_mandel": ([vp, u64, P(caf_mandel_args), u32, u32, vp, vp,
                                 P(caf_offload_times)], C.c_int),
+        "caf_offload_mandel_noalloc": ([vp, u64, P(caf_mandel_args), u32, u32, vp,
+                                        P(caf_offload_times)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -360,6 +366,23 @@ class System:
                                        out.ctypes.data, C.byref(t))
         if st != OK:
             raise CafError("caf_offload_mandel", st)
+        return out, {"total_ns": t.total_ns, "gpu_done_ns": t.gpu_done_ns,
+                     "cpu_done_ns": t.cpu_done_ns}
+
+    def offload_mandel_noalloc(self, actor, image: "caf_mandel_args", gpu_rows: int,
+                               cpu_threads=0, out=None):
+        """caf_offload_mandel_noalloc: the same split, the GPU share staged
+        in the library's fixed device array (no allocation in the call).
+        Returns (uint16 [height, width], times dict in ns)."""
+        if out is None:
+            out = np.zeros((image.height, image.width), np.uint16)
+        assert out.dtype == np.uint16 and out.flags.c_contiguous
+        assert out.size >= image.height * image.width
+        t = caf_offload_times()
+        st = self.L.caf_offload_mandel_noalloc(self.h, actor, C.byref(image), gpu_rows,
+                                               cpu_threads, out.ctypes.data, C.byref(t))
+        if st != OK:
+            raise CafError("caf_offload_mandel_noalloc", st)
         return out, {"total_ns": t.total_ns, "gpu_done_ns": t.gpu_done_ns,
                      "cpu_done_ns": t.cpu_done_ns}
 

@@ -209,6 +209,14 @@ struct CpuPool;
 void cpu_pool_destroy(CpuPool* p);
 CpuPool*& cpu_pool_of(caf_gpu_system* s);
 std::mutex& offload_mu_of(caf_gpu_system* s);  // one split at a time per system
+int device_of(const caf_gpu_system* s);
+// The fixed staging array of caf_offload_mandel_noalloc and the bound on its
+// request table (public limits, caf_gpu.h).
+constexpr uint64_t kOffloadStageBytes = CAF_OFFLOAD_NOALLOC_STAGE_BYTES;
+constexpr uint32_t kOffloadNoallocMaxTiles = CAF_OFFLOAD_NOALLOC_MAX_ROWS / 64;
+// Looks up the address of `device`'s copy of that array (once per device;
+// the device must be current).  CAF_OK or CAF_E_DEVICE.
+int offload_stage_setup(int device);
 
 }  // namespace cafgpu
 

@@ -147,11 +147,45 @@ struct CpuPool {
 
 void cpu_pool_destroy(CpuPool* p) { delete p; }
 
+// Staging for caf_offload_mandel_noalloc: the GPU share's replies land here
+// instead of in a caller's buffer.  Every device the library runs on holds
+// its own copy until the process ends.  Host code never uses the array's
+// name as an address: the address of each device's copy is looked up once,
+// with that device current, and kept in offload_stage_ptr.
+static __device__ __align__(256) uint16_t offload_stage[kOffloadStageBytes / sizeof(uint16_t)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex stage_mu;
+void* stage_ptr[kMaxDevices] = {};
+}  // namespace
+
+int offload_stage_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return CAF_E_INVALID;
+  std::lock_guard<std::mutex> g(stage_mu);
+  if (stage_ptr[device]) return CAF_OK;
+  void* p = nullptr;
+  // the caller (caf_gpu_init) has made `device` current
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(offload_stage)) != hipSuccess || !p)
+    return CAF_E_DEVICE;
+  stage_ptr[device] = p;
+  return CAF_OK;
+}
+
+static uint16_t* offload_stage_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(stage_mu);
+  return static_cast<uint16_t*>(stage_ptr[device]);
+}
+
 }  // namespace cafgpu
 
 using cafgpu::CpuPool;
+using cafgpu::kOffloadNoallocMaxTiles;
+using cafgpu::kOffloadStageBytes;
 
 constexpr uint32_t kMaxCpuThreads = 1024;
+constexpr uint32_t kOffloadTileRows = 64;  // rows per GPU request of a split
 
 extern "C" int caf_cpu_mandel_rows(const caf_mandel_args* a, uint32_t row_begin, uint32_t row_end,
                                    uint16_t* out_host) {
@@ -161,19 +195,20 @@ extern "C" int caf_cpu_mandel_rows(const caf_mandel_args* a, uint32_t row_begin,
   return CAF_OK;
 }
 
-extern "C" int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor,
-                                  const caf_mandel_args* image, uint32_t gpu_rows,
-                                  uint32_t cpu_threads, uint16_t* dev_stage, uint16_t* out_host,
-                                  caf_offload_times* times) {
-  if (!sys || !args_ok(image) || image->row0 != 0 || image->rows != image->height ||
-      gpu_rows > image->height || !out_host || (gpu_rows && !dev_stage))
-    return CAF_E_INVALID;
-  if (cpu_threads > kMaxCpuThreads) return CAF_E_INVALID;
-  if (cpu_threads == 0) cpu_threads = std::max(1u, std::thread::hardware_concurrency());
+namespace {
+
+// One split.  stage: device memory for the GPU share's replies.
+// may_start_pool: whether the CPU actors' pool may be (re)created here.
+// tile_args / futs: room for ceil(gpu_rows / 64) entries.
+int offload_run(caf_gpu_system* sys, caf_actor gpu_actor, const caf_mandel_args* image,
+                uint32_t gpu_rows, uint32_t cpu_threads, uint16_t* stage, uint16_t* out_host,
+                caf_offload_times* times, bool may_start_pool, caf_mandel_args* tile_args,
+                caf_future** futs) {
   const uint32_t width = image->width, height = image->height;
   std::lock_guard<std::mutex> one_at_a_time(cafgpu::offload_mu_of(sys));
   CpuPool*& pool = cafgpu::cpu_pool_of(sys);
   if (gpu_rows < height && (!pool || pool->nthreads != cpu_threads)) {
+    if (!may_start_pool) return CAF_E_INVALID;
     delete pool;
     pool = nullptr;
     try {
@@ -184,36 +219,34 @@ extern "C" int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor,
   }
   const int64_t t0 = now_ns();
   if (gpu_rows < height) pool->post(*image, gpu_rows, height, out_host + (uint64_t)gpu_rows * width);
-  // The GPU share: requests of at most 64 rows, replies into dev_stage.
+  // The GPU share: requests of at most kOffloadTileRows rows, replies into stage.
   int rc = CAF_OK;
   int64_t t_gpu = t0;
   if (gpu_rows) {
-    constexpr uint32_t kTileRows = 64;
-    std::vector<caf_future*> futs;
-    std::vector<caf_mandel_args> targs((gpu_rows + kTileRows - 1) / kTileRows);
-    for (uint32_t i = 0, r = 0; r < gpu_rows; ++i, r += kTileRows) {
-      caf_mandel_args& ta = targs[i];
+    uint32_t nf = 0;
+    for (uint32_t r = 0; r < gpu_rows; r += kOffloadTileRows) {
+      caf_mandel_args& ta = tile_args[nf];
       ta = *image;
       ta.row0 = r;
-      ta.rows = std::min(kTileRows, gpu_rows - r);
-      caf_buf out{dev_stage + (uint64_t)r * width, (uint64_t)ta.rows * width, CAF_U16, 1};
+      ta.rows = std::min(kOffloadTileRows, gpu_rows - r);
+      caf_buf out{stage + (uint64_t)r * width, (uint64_t)ta.rows * width, CAF_U16, 1};
       caf_future* f = nullptr;
       const int st = caf_gpu_request(sys, gpu_actor, 0, &ta, sizeof ta, nullptr, 0, &out, 0, &f);
       if (st != CAF_OK) {
         rc = st;
         break;
       }
-      futs.push_back(f);
+      futs[nf++] = f;
     }
-    for (caf_future* f : futs) {
+    for (uint32_t i = 0; i < nf; ++i) {
       caf_buf res{};
       int32_t st = CAF_OK;
-      if (caf_future_wait(f, -1, &res, &st) != CAF_OK) st = CAF_E_TIMEOUT;
+      if (caf_future_wait(futs[i], -1, &res, &st) != CAF_OK) st = CAF_E_TIMEOUT;
       if (st != CAF_OK && rc == CAF_OK) rc = st;
-      caf_future_release(f);
+      caf_future_release(futs[i]);
     }
     if (rc == CAF_OK &&
-        hipMemcpy(out_host, dev_stage, (uint64_t)gpu_rows * width * sizeof(uint16_t),
+        hipMemcpy(out_host, stage, (uint64_t)gpu_rows * width * sizeof(uint16_t),
                   hipMemcpyDeviceToHost) != hipSuccess)
       rc = CAF_E_DEVICE;
     t_gpu = now_ns();
@@ -230,4 +263,43 @@ extern "C" int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor,
     times->cpu_done_ns = t_cpu - t0;
   }
   return rc;
+}
+
+}  // namespace
+
+extern "C" int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor,
+                                  const caf_mandel_args* image, uint32_t gpu_rows,
+                                  uint32_t cpu_threads, uint16_t* dev_stage, uint16_t* out_host,
+                                  caf_offload_times* times) {
+  if (!sys || !args_ok(image) || image->row0 != 0 || image->rows != image->height ||
+      gpu_rows > image->height || !out_host || (gpu_rows && !dev_stage))
+    return CAF_E_INVALID;
+  if (cpu_threads > kMaxCpuThreads) return CAF_E_INVALID;
+  if (cpu_threads == 0) cpu_threads = std::max(1u, std::thread::hardware_concurrency());
+  const uint32_t ntiles = (gpu_rows + kOffloadTileRows - 1) / kOffloadTileRows;
+  std::vector<caf_mandel_args> targs(ntiles);
+  std::vector<caf_future*> futs(ntiles);
+  return offload_run(sys, gpu_actor, image, gpu_rows, cpu_threads, dev_stage, out_host, times,
+                     true, targs.data(), futs.data());
+}
+
+extern "C" int caf_offload_mandel_noalloc(caf_gpu_system* sys, caf_actor gpu_actor,
+                                          const caf_mandel_args* image, uint32_t gpu_rows,
+                                          uint32_t cpu_threads, uint16_t* out_host,
+                                          caf_offload_times* times) {
+  if (!sys || !args_ok(image) || image->row0 != 0 || image->rows != image->height ||
+      gpu_rows > image->height || !out_host)
+    return CAF_E_INVALID;
+  if (cpu_threads > kMaxCpuThreads) return CAF_E_INVALID;
+  if (cpu_threads == 0) cpu_threads = std::max(1u, std::thread::hardware_concurrency());
+  // the limits of the fixed staging array and of the on-stack request table
+  if ((uint64_t)gpu_rows * image->width * sizeof(uint16_t) > kOffloadStageBytes ||
+      gpu_rows > kOffloadNoallocMaxTiles * kOffloadTileRows)
+    return CAF_E_INVALID;
+  uint16_t* stage = cafgpu::offload_stage_ptr(cafgpu::device_of(sys));
+  if (!stage) return CAF_E_DEVICE;
+  caf_mandel_args targs[kOffloadNoallocMaxTiles];
+  caf_future* futs[kOffloadNoallocMaxTiles];
+  return offload_run(sys, gpu_actor, image, gpu_rows, cpu_threads, stage, out_host, times,
+                     false, targs, futs);
 }

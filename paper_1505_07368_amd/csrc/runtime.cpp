@@ -301,6 +301,7 @@ struct caf_gpu_system {
 namespace cafgpu {
 CpuPool*& cpu_pool_of(caf_gpu_system* s) { return s->cpu_pool; }
 std::mutex& offload_mu_of(caf_gpu_system* s) { return s->offload_mu; }
+int device_of(const caf_gpu_system* s) { return s->device; }
 }  // namespace cafgpu
 
 namespace {
@@ -1037,6 +1038,8 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
     if (t != 0 && t != 64 && t != 128) return CAF_E_INVALID;
   if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT) return CAF_E_INVALID;
   if (hipSetDevice(cfg->device) != hipSuccess) return CAF_E_DEVICE;
+  // once per device: the address of this device's no-alloc staging array
+  if (const int st = cafgpu::offload_stage_setup(cfg->device); st != CAF_OK) return st;
   caf_gpu_system* s = new caf_gpu_system();
   s->cfg = *cfg;
   s->device = cfg->device;
