@@ -375,11 +375,18 @@ def offload_leg(cg, torch, reps=3, threads=None):
         s.shutdown()
 
 
-def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 << 30):
+def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 << 30,
+                blocking=False):
     """Open-loop Poisson arrivals: 70 % Mandelbrot squares (64^2..512^2,
     max_iter 256..4096, boundary viewports, fp32), 30 % fp32 GEMM with n in
-    {32..512}; admission by HBM budget and mailbox slots, non-blocking
-    (refused requests are counted); latency from the scheduled arrival."""
+    {32..512}; admission by HBM budget and mailbox slots; latency from the
+    scheduled arrival.  Non-blocking: a request that does not fit is refused
+    (counted).  Blocking: it waits, in arrival order, until earlier replies
+    free a slot and arena memory.  Replies are library-allocated from the
+    arena, so the budget binds.  The work done is counted over the completed
+    requests: Mandelbrot iterations (each message's exact count sum, from a
+    closed-loop pass over the same messages before the timed run) and GEMM
+    flops (2 n^3)."""
     from paper_1505_07368_amd import gen
     d = gen.serving_mix_arrays(seed, rate, duration_s)
     cnt = d["arrival_ns"].size
@@ -389,7 +396,7 @@ def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 <<
     for n in gen.SERVE_GEMM_N:  # eight distinct input pairs per size
         pool[n] = [(torch.rand(n * n, generator=gg, device="cuda") * 2 - 1,
                     torch.rand(n * n, generator=gg, device="cuda") * 2 - 1) for _ in range(8)]
-    s = cg.System(mode="persistent", arena_bytes=budget, ring_slots=ring, blocking=False)
+    s = cg.System(mode="persistent", arena_bytes=budget, ring_slots=ring, blocking=blocking)
     try:
         m = s.spawn(cg.BHV_MANDELBROT)
         gm = s.spawn(cg.BHV_GEMM)
@@ -427,20 +434,54 @@ def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 <<
                                 gargs.ctypes.data + idx * gargs.itemsize)
         msgs["args_bytes"] = np.where(ism, margs.itemsize, gargs.itemsize)
         msgs["in_"] = np.where(ism, 0, bufs.ctypes.data + idx * 2 * bufs.itemsize)
-        torch.cuda.synchronize()
         keep = (margs, gargs, bufs, pool)
-        rc, lat, st, el = cg.drive_array(s, msgs, keep, window=ring, arrival_ns=d["arrival_ns"])
+        iters = mandel_work(cg, torch, s, msgs[ism], keep, d["side"][ism], window=ring // 2)
+        torch.cuda.synchronize()
+        # the driver's own bookkeeping never limits: the library admits
+        rc, lat, st, el = cg.drive_array(s, msgs, keep, window=cnt, arrival_ns=d["arrival_ns"])
         ok = st == cg.OK
         rej = st == cg.E_OVERLOAD
         assert ((st == cg.OK) | rej).all(), np.unique(st)
         p50, p99 = percentiles(lat[ok])
         pm50, pm99 = percentiles(lat[ok & ism])
-        return {"offered_per_s": cnt / duration_s, "messages": int(cnt),
+        gn = d["gemm_n"].astype(np.float64)
+        return {"offered_per_s": cnt / duration_s, "messages": int(cnt), "budget_bytes": budget,
+                "admission": "blocking" if blocking else "non-blocking",
                 "completed": int(ok.sum()), "rejected": int(rej.sum()),
                 "goodput_per_s": float(ok.sum()) / el, "elapsed_s": el,
-                "p50_us": p50, "p99_us": p99, "mandel_p50_us": pm50, "mandel_p99_us": pm99}
+                "p50_us": p50, "p99_us": p99, "mandel_p50_us": pm50, "mandel_p99_us": pm99,
+                "mandel_giter_s": float(iters[ok[ism]].sum()) / el / 1e9,
+                "gemm_tflops": float((2 * gn[ok & ~ism] ** 3).sum()) / el / 1e12}
     finally:
         s.shutdown()
+
+
+def mandel_work(cg, torch, s, msgs, keep, side, window, chunk_px=1 << 27):
+    """Exact iterations of each Mandelbrot message: messages of one square
+    size at a time are run in closed-loop chunks with their replies written
+    into a device pool [k, side * side], and each reply's counts are summed
+    (counts <= 4096 fit int16)."""
+    out = np.zeros(msgs.size, np.int64)
+    side = side.astype(np.int64)
+    for sd in np.unique(side):
+        sel = np.nonzero(side == sd)[0]
+        px = int(sd * sd)
+        k = max(1, min(len(sel), chunk_px // px))
+        for c0 in range(0, len(sel), k):
+            ids = sel[c0:c0 + k]
+            buf = torch.empty((len(ids), px), dtype=torch.int16, device="cuda")
+            part = msgs[ids].copy()
+            part["out"]["data"] = buf.data_ptr() + 2 * px * np.arange(len(ids), dtype=np.uint64)
+            part["out"]["numel"] = px
+            part["out"]["dtype"] = cg.U16
+            part["out"]["on_device"] = 1
+            torch.cuda.synchronize()
+            rc, _, st, _ = cg.drive_array(s, part, keep, window=min(len(part), window))
+            assert rc == cg.OK and (st == cg.OK).all(), (rc, np.unique(st))
+            torch.cuda.synchronize()
+            out[ids] = buf.to(torch.int32).sum(1, dtype=torch.int64).cpu().numpy()
+            del buf
+    return out
 
 
 def cpu_oracle_tile(args):
@@ -664,6 +705,11 @@ def main():
             dur = min(2.0, 2e5 / rate)
             log(f"[bench] serving {rate:g}/s for {dur:g} s")
             serving[f"{rate:g}"] = serving_leg(cg, torch, rate, duration_s=dur)
+        # a 64 MiB budget: admission binds on arena memory
+        for blocking in (False, True):
+            log(f"[bench] serving 1e5/s for 0.5 s, 64 MiB budget, blocking={blocking}")
+            serving["1e5_64MiB_" + ("blocking" if blocking else "nonblocking")] = serving_leg(
+                cg, torch, 1e5, duration_s=0.5, budget=64 << 20, blocking=blocking)
         result["serving"] = serving
     if "offload" in legs:
         result["offload"] = offload_leg(cg, torch)

@@ -291,8 +291,12 @@ double caf_gpu_drain_kernel_ms(caf_gpu_system* sys, uint64_t* launches);
  *     device-side forwarding: every message's reply is re-sent by the host
  *     to hop_actor[0], then hop_actor[1] (shape args rows = cols = n).
  * latency_ns[i] (optional) gets reply time - issue/scheduled time;
- * status[i] (optional) the reply status.  Returns CAF_OK or the first
- * call-time error. */
+ * status[i] (optional) the reply status.  Admission: the driver never waits
+ * inside a request.  With a blocking system a request that does not fit
+ * yet (mailbox or arena full) waits at the head of the driver's queue, in
+ * order, and is retried as replies are harvested and released; with a
+ * non-blocking system it is refused (status CAF_E_OVERLOAD, not counted as
+ * an error).  Returns CAF_OK or the first other call-time error. */
 typedef struct {
   caf_actor actor;
   uint32_t sender;

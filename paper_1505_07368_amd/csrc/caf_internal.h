@@ -221,10 +221,15 @@ int offload_stage_setup(int device);
 }  // namespace cafgpu
 
 // Request entry used by the native driver: like caf_gpu_request, and the
-// poller pushes `tag` into `q` when the future resolves.
+// poller pushes `tag` into `q` when the future resolves.  try_only: never
+// wait for admission; a message that does not fit yet (mailbox or arena
+// full, but it would fit an empty arena) returns kTryLater and is not
+// counted as refused.
+constexpr int kTryLater = -100;
 int cafgpu_request_tagged(caf_gpu_system* sys, caf_actor dst, uint32_t sender, const void* args,
                           uint64_t args_bytes, const caf_buf* in, uint32_t n_in,
                           const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut,
-                          cafgpu::DriveQ* q, uint32_t tag);
+                          cafgpu::DriveQ* q, uint32_t tag, bool try_only = false);
+bool cafgpu_blocking(const caf_gpu_system* sys);
 int64_t cafgpu_future_issue_ns(const caf_future* f);
 int64_t cafgpu_future_done_ns(const caf_future* f);

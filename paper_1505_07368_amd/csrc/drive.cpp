@@ -10,6 +10,15 @@
 //  * host-mediated chains: each reply is re-sent by the host to the next
 //    pipeline actor, the comparison point for device-side forwarding.
 //
+// Admission.  The driver never waits inside a request call (a request
+// blocked on arena space that only the driver's own harvest would free
+// could never return).  With a blocking system, a request that does not fit
+// yet stays at the head of the driver's queue -- later messages keep their
+// order behind it -- and is retried after the next replies are harvested,
+// which frees their slots and arena buffers: messages are admitted as room
+// frees up, and the open-loop latency includes that wait.  With a
+// non-blocking system, a refused request is final (status CAF_E_OVERLOAD).
+//
 // Replies are harvested through a completion queue that the poller thread
 // fills with the tags of resolved requests, so harvesting costs O(1) per
 // reply whatever the window.
@@ -79,17 +88,20 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
     ++done;
   };
 
-  auto issue_first = [&](uint64_t i, int64_t t_sched) {
+  const bool wait_for_room = cafgpu_blocking(sys);
+  // Issues message i; false if it does not fit yet (blocking system only).
+  auto issue_first = [&](uint64_t i, int64_t t_sched) -> bool {
     const caf_msg& m = msgs[i];
     const uint32_t tag = free_tags.back();
     caf_future* f = nullptr;
     const bool final_here = chain_hops == 0;
     const int st = cafgpu_request_tagged(sys, m.actor, m.sender, m.args, m.args_bytes, m.in,
                                          m.n_in, (final_here && m.out.data) ? &m.out : nullptr,
-                                         m.forward_to, &f, &q, tag);
+                                         m.forward_to, &f, &q, tag, wait_for_room);
+    if (st == kTryLater) return false;
     if (st != CAF_OK) {
       fail(i, st);
-      return;
+      return true;
     }
     free_tags.pop_back();
     Pending& p = pend[tag];
@@ -97,6 +109,7 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
     p.f = f;
     p.idx = i;
     p.t_ref = t_sched >= 0 ? t_sched : cafgpu_future_issue_ns(f);
+    return true;
   };
 
   // Handles the resolved request of tag k.
@@ -155,18 +168,17 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
 
   while (done < count) {
     bool issued = false;
-    if (!arrival_ns) {
-      while (next < count && !free_tags.empty()) {
-        issue_first(next++, -1);
-        issued = true;
-      }
-    } else {
+    // messages [next, due) may be issued now, in order
+    uint64_t due = count;
+    if (arrival_ns) {
       const int64_t now = now_ns() - t_start;
-      while (next < count && arrival_ns[next] <= now && !free_tags.empty()) {
-        issue_first(next, t_start + arrival_ns[next]);
-        ++next;
-        issued = true;
-      }
+      due = next;
+      while (due < count && arrival_ns[due] <= now) ++due;
+    }
+    while (next < due && !free_tags.empty()) {
+      if (!issue_first(next, arrival_ns ? t_start + arrival_ns[next] : -1)) break;
+      ++next;
+      issued = true;
     }
     if (!harvest() && !issued) _mm_pause();
   }

@@ -739,7 +739,8 @@ bool launch_graph(caf_gpu_system* s, const Desc* sd, const uint32_t* nt, uint32_
 
 int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
            uint64_t args_bytes, const caf_buf* in, uint32_t n_in, const caf_buf* out_buf,
-           caf_actor forward_to, caf_future** fut, bool is_request, DriveQ* q, uint32_t tag) {
+           caf_actor forward_to, caf_future** fut, bool is_request, DriveQ* q, uint32_t tag,
+           bool try_only = false) {
   (void)sender;  // FIFO per (sender, actor) follows from the single ring order
   if (!s) return CAF_E_INVALID;
   if (n_in > 2 || (n_in && !in)) return CAF_E_INVALID;
@@ -847,6 +848,7 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
       reclaim_all = true;  // everything finished goes back before refusing
       continue;
     }
+    if (try_only) return kTryLater;  // the caller waits and retries: not a refusal
     if (!s->cfg.blocking) {
       s->st_rejected++;
       return CAF_E_OVERLOAD;
@@ -989,18 +991,19 @@ int submit(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
 int cafgpu_request_tagged(caf_gpu_system* s, caf_actor dst, uint32_t sender, const void* args,
                           uint64_t args_bytes, const caf_buf* in, uint32_t n_in,
                           const caf_buf* out_or_null, caf_actor forward_to, caf_future** fut,
-                          DriveQ* q, uint32_t tag) {
+                          DriveQ* q, uint32_t tag, bool try_only) {
   if (!fut) return CAF_E_INVALID;
   *fut = nullptr;
   try {
     return submit(s, dst, sender, args, args_bytes, in, n_in, out_or_null, forward_to, fut,
-                  true, q, tag);
+                  true, q, tag, try_only);
   } catch (...) {  // thrown before the message is published: nothing is pending
     return CAF_E_OVERLOAD;
   }
 }
 
 int64_t cafgpu_future_issue_ns(const caf_future* f) { return f->t_issue; }
+bool cafgpu_blocking(const caf_gpu_system* s) { return s->cfg.blocking != 0; }
 int64_t cafgpu_future_done_ns(const caf_future* f) { return f->t_done; }
 
 extern "C" {
