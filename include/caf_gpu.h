@@ -249,6 +249,18 @@ int caf_gpu_quit(caf_gpu_system* sys, caf_actor actor, uint32_t exit_reason);
 int caf_gpu_become(caf_gpu_system* sys, caf_actor actor, int32_t behavior,
                    const caf_spawn_args* args);
 
+/* Holds the drain back (hold != 0) or lets it go (hold = 0); ring forms
+ * only (CAF_E_INVALID for the plain forms, which launch at submit time).
+ * While held, no drain kernel is launched: accepted messages wait in the
+ * mailbox, up to ring_slots of them (beyond that requests wait or are
+ * refused, as when the mailbox is full).  Letting go launches one drain for
+ * everything that waited, which takes it in batches of max_batch -- the
+ * caller sets a batch boundary, the way the scheduler's max_msgs bounds
+ * what one actor run takes from its mailbox (Sec. 6).  A drain kernel that
+ * is already running keeps draining; hold affects the next launch.
+ * caf_gpu_drain waits for held messages (and times out while held). */
+int caf_gpu_hold(caf_gpu_system* sys, int32_t hold);
+
 /* Blocks until every accepted message is handled (all replies delivered). */
 int caf_gpu_drain(caf_gpu_system* sys, int64_t timeout_ns);
 

@@ -30,7 +30,7 @@ EXPORTED = ["caf_gpu_init", "caf_gpu_spawn", "caf_gpu_send", "caf_gpu_request",
             "caf_gpu_quit", "caf_gpu_drain", "caf_gpu_shutdown", "caf_gpu_strerror",
             "caf_gpu_get_stats", "caf_gpu_drain_kernel_ms", "caf_gpu_drive",
             "caf_cpu_mandel_rows", "caf_offload_mandel", "caf_gpu_become",
-            "caf_offload_mandel_noalloc"]
+            "caf_offload_mandel_noalloc", "caf_gpu_hold"]
 # limits of caf_offload_mandel_noalloc (caf_gpu.h)
 OFFLOAD_NOALLOC_STAGE_BYTES = 16 << 20
 OFFLOAD_NOALLOC_MAX_ROWS = 16384
@@ -125,6 +125,7 @@ def load():
                           C.c_int),
         "caf_cpu_mandel_rows": ([P(caf_mandel_args), u32, u32, vp], C.c_int),
         "caf_gpu_become": ([vp, u64, i32, P(caf_spawn_args)], C.c_int),
+        "caf_gpu_hold": ([vp, i32], C.c_int),
         "caf_offload_mandel": ([vp, u64, P(caf_mandel_args), u32, u32, vp, vp,
                                 P(caf_offload_times)], C.c_int),
         "caf_offload_mandel_noalloc": ([vp, u64, P(caf_mandel_args), u32, u32, vp,
@@ -329,6 +330,11 @@ class System:
         ab = bytes(args) if args is not None else b""
         bufs = self._bufs(inputs)
         return self.L.caf_gpu_send(self.h, actor, sender, ab, len(ab), bufs, len(inputs))
+
+    def hold(self, on: bool = True) -> int:
+        """caf_gpu_hold: while held, messages wait in the mailbox; letting
+        go runs them as one drain launch."""
+        return self.L.caf_gpu_hold(self.h, 1 if on else 0)
 
     def drain(self, timeout_s: float = 60.0) -> int:
         return self.L.caf_gpu_drain(self.h, int(timeout_s * 1e9))

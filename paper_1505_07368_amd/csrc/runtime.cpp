@@ -289,6 +289,7 @@ struct caf_gpu_system {
   uint32_t gemm_tile = 0;
   uint32_t grid_full = 0, grid_light = 0;  // drain-kernel workgroups per variant
   std::atomic<bool> need_full{false};       // a GEMM actor exists
+  std::atomic<bool> held{false};            // caf_gpu_hold: no new drain launch
   bool last_full = false;                   // variant of the latest drain launch (launch_mu)
   hipEvent_t handover = nullptr;            // light -> full launch ordering (launch_mu)
   std::map<PlainShape, PlainGraph> graphs;  // CAF_MODE_PLAIN_GRAPH, guarded by mu
@@ -406,6 +407,7 @@ bool drain_running(caf_gpu_system* s) {
 
 // Launches the drain kernel if it is not running (ring modes).
 void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
+  if (s->held.load(std::memory_order_acquire)) return;
   if (drain_running(s)) return;  // fast path, no lock
   std::lock_guard<std::mutex> g(s->launch_mu);
   if (drain_running(s)) return;
@@ -1282,6 +1284,14 @@ int caf_gpu_quit(caf_gpu_system* s, caf_actor actor, uint32_t /*exit_reason*/) {
   const uint32_t idx = (uint32_t)(actor - 1);
   s->actors[idx].alive = false;
   __atomic_fetch_and(&s->hctl->alive[idx >> 5], ~(1u << (idx & 31)), __ATOMIC_SEQ_CST);
+  return CAF_OK;
+}
+
+int caf_gpu_hold(caf_gpu_system* s, int32_t hold) {
+  if (!s) return CAF_E_INVALID;
+  if (s->plain()) return CAF_E_INVALID;  // plain forms launch at submit time
+  s->held.store(hold != 0, std::memory_order_release);
+  if (!hold) ensure_drain(s, true);  // one launch for everything that waited
   return CAF_OK;
 }
 

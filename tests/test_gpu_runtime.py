@@ -549,3 +549,44 @@ def test_degenerate_and_maximum_arguments(sysm):
         st, c1 = sysm.request(g, cg.caf_gemm_args(1, code), inputs=[a1, b1]).result()
         assert st == cg.OK and float(c1.cpu()[0]) == -6.0
     assert sysm.drain(30) == cg.OK
+
+
+@pytest.mark.parametrize("mode", ["batched", "persistent"])
+def test_hold_collects_one_batch(mode):
+    """caf_gpu_hold: held messages wait in the mailbox (no reply, no new
+    launch); letting go runs them in one drain launch, each reply equal to
+    the oracle's."""
+    import time
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    with cg.System(mode=mode, arena_bytes=64 << 20, ring_slots=256, idle_exit_us=50) as s:
+        g = s.spawn(cg.BHV_GEMM)
+        e = s.spawn(cg.BHV_NOOP)
+        # a first message, so a launch has come and gone
+        st, v = s.request(e, inputs=[np.array([1], np.int32)]).result()
+        assert st == cg.OK
+        assert s.drain() == cg.OK
+        s.drain_kernel_ms()  # waits until that launch has exited
+        before = s.stats()["drain_launches"]
+        assert s.hold(True) == cg.OK
+        pairs = [gen.gemm_pair(700 + i, 96) for i in range(24)]
+        dev = [(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()) for A, B in pairs]
+        torch.cuda.synchronize()
+        futs = [s.request(g, cg.caf_gemm_args(96, cg.F32), inputs=list(ab)) for ab in dev]
+        futs += [s.request(e, inputs=[np.array([i, -i], np.int32)]) for i in range(40)]
+        time.sleep(0.05)
+        assert not any(f.poll()[0] for f in futs)  # nothing ran while held
+        assert s.drain(timeout_s=0.01) == cg.E_TIMEOUT
+        assert s.stats()["drain_launches"] == before
+        assert s.hold(False) == cg.OK
+        for (A, B), f in zip(pairs, futs[:24]):
+            st, C = f.result()
+            assert st == cg.OK
+            assert rel_fro(C.cpu().numpy().reshape(96, 96), oracle.gemm(A, B)) <= 1e-5
+        for i, f in enumerate(futs[24:]):
+            st, v = f.result()
+            assert st == cg.OK and v.tolist() == [i, -i]
+        assert s.drain() == cg.OK
+        assert s.stats()["drain_launches"] == before + 1
+    with cg.System(mode="plain", arena_bytes=16 << 20) as p:
+        assert p.hold(True) == cg.E_INVALID
