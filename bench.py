@@ -590,6 +590,9 @@ def main():
                     help="comma list of the legs to run beside the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--gemm-dtypes", default="f32,bf16", help="GEMM leg input types")
+    ap.add_argument("--headline-fp", default="f32", choices=("f32", "f64"),
+                    help="precision of the headline leg (f64: for profiling the double "
+                    "path; the reported metric is defined in f32)")
     ap.add_argument("--interior", action="store_true",
                     help="with --quick: also time the no-divergence interior viewport")
     ap.add_argument("--dispersion", type=int, default=100,
@@ -620,8 +623,10 @@ def main():
         log("[bench] autotune (mandelbrot work tile, grid)")
         tuned["mandel"] = autotune.tune_mandel(torch, vps, cache_path=cache)
     log("[bench] batched fp32 (headline)")
-    head = mandel_leg(cg, torch, "batched", cg.F32, args.steps, args.warmup, seeds, True,
-                      tune=tuned.get("mandel"), dispersion_reps=args.dispersion)
+    hfp = args.headline_fp
+    head = mandel_leg(cg, torch, "batched", cg.F32 if hfp == "f32" else cg.F64, args.steps,
+                      args.warmup, seeds, True, tune=tuned.get("mandel"),
+                      dispersion_reps=args.dispersion)
     result = {
         "metric": "GPU-actor msgs/s + Mandelbrot Giter/s; p50/p99 reply latency vs 1-launch/msg",
         "value": round(head["giter_s"], 2),
@@ -633,11 +638,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": hfp,
         "data": "synthetic",
         "config": {"workload": "mandelbrot 1920x1080 max_iter 1000, 8 seeded boundary "
-                               "viewports x 17 row-tile messages (64 rows, last 56), fp32, "
-                               "batched mailbox drain",
+                               "viewports x 17 row-tile messages (64 rows, last 56), "
+                               f"{'fp32' if hfp == 'f32' else 'fp64'}, batched mailbox drain",
                    "images": len(seeds), "tile_rows": 64, "max_iter": 1000,
                    "messages_per_step": head["messages_per_step"],
                    "iters_per_step": head["iters_per_step"]},
@@ -656,8 +661,9 @@ def main():
         achieved = ops / (kms * 1e-3)
         result["roofline"] = {
             "bound": "alu", "achieved": round(achieved / 1e12, 3),
-            "peak": round(VALU_PEAK["f32"] / 1e12, 3), "unit": "TFLOP/s",
-            "frac": round(achieved / VALU_PEAK["f32"], 4), "traffic": measured_traffic(),
+            "peak": round(VALU_PEAK[hfp] / 1e12, 3), "unit": "TFLOP/s",
+            "frac": round(achieved / VALU_PEAK[hfp], 4),
+            "traffic": measured_traffic() if hfp == "f32" else None,
             "kernel": "drain_kernel_light", "launches": head["kernel_launches"],
             "avg_launch_ms": round(per_launch_ms, 4), "ops_per_iter": OPS_PER_ITER,
             "ops_per_launch": head["iters_per_step"] * OPS_PER_ITER}
