@@ -462,8 +462,11 @@ struct DrainLds {
   uint16_t hactor[kMaxBatch];
   uint64_t hx[kMaxBatch];
   uint16_t hidx[kMaxBatch];
+  // echo entries with inline input and reply, answered by the drain itself
+  uint8_t inl[kMaxBatch];
   uint32_t nh;
   uint32_t any_hash;  // some entry is one
+  uint32_t any_echo;  // some entry is an inline echo
   uint64_t hpos;
   uint32_t first_bad;  // light launch: first entry it cannot run
   uint32_t any_dead;   // some entry's actor looked dead in the snapshot
@@ -512,6 +515,9 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
   __syncthreads();
   return total;
 }
+
+// Largest drain pass whose inline echoes the drain answers itself.
+constexpr uint32_t kDrainEchoMax = 4;
 
 // A workgroup's reservation of claimed tile indices (see "claiming work
 // tiles" below).
@@ -594,8 +600,10 @@ __device__ void run_hash_entries_locked(KArgsC& a, DrainLds& L, uint32_t cnt) {
   if (lane == 0) L.nh = nh;
 }
 
-// The replies of the entries run by run_hash_entries_locked: one completion
-// position reservation, then the records in parallel (whole workgroup).
+// The replies of the entries the drain answers itself -- the hash-chain
+// entries run by run_hash_entries_locked and the inline echo entries -- one
+// completion position reservation, then the records in parallel (whole
+// workgroup).
 __device__ void complete_hash_entries(KArgsC& a, DrainLds& L) {
   const uint32_t t = threadIdx.x;
   const uint32_t nh = L.nh;
@@ -606,9 +614,11 @@ __device__ void complete_hash_entries(KArgsC& a, DrainLds& L) {
   __syncthreads();
   for (uint32_t j = t; j < nh; j += kThreads) {
     const uint32_t i = L.hidx[j];
-    const uint64_t v[2] = {L.hx[i], 0ull};
-    write_completion_at(a, L.hpos + j, a.slots[L.slot[i]].d.req_id, CAF_OK,
-                        reinterpret_cast<const uint8_t*>(v));
+    const Desc& e = a.slots[L.slot[i]].d;  // written by this workgroup this pass
+    uint64_t v[2] = {L.hx[i], 0ull};
+    // an inline echo replies with its inline input (at most four int32)
+    if (L.inl[i]) __builtin_memcpy(v, e.p.raw, sizeof v);
+    write_completion_at(a, L.hpos + j, e.req_id, CAF_OK, reinterpret_cast<const uint8_t*>(v));
   }
 }
 
@@ -627,6 +637,7 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
   if (t >= 64 && t < 64 + kAliveWords) L.alive[t - 64] = ld_sys(&a.hctl->alive[t - 64]);
   if (t == 0) L.any_dead = 0;
   if (t == 0) L.any_hash = 0;
+  if (t == 0) L.any_echo = 0;
   if (t == 0) {
     // All five loads are in flight together; one system-scope acquire fence
     // after them orders the entry reads below after the tail (each acquire
@@ -678,6 +689,22 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
                            (e.flags & (DF_INLINE_OUT | DF_SEND)) != 0;
     L.hactor[i] = hash_here ? (uint16_t)(e.actor + 1u) : (uint16_t)0;
     if (hash_here) L.any_hash = 1;
+    // An echo whose input and reply both travel inline (a ping-pong
+    // message) in a pass of at most kDrainEchoMax entries: the drain answers
+    // it itself, with no tile, publication or claim, which is what a reply
+    // that is waited for needs.  In larger passes the echoes go the tile
+    // way, where many workgroups write their replies while the next pass
+    // drains.  An echo keeps no state, so answering it here instead of as a
+    // tile changes no observable order.
+    const bool echo_here = alive && L.cnt <= kDrainEchoMax && e.behavior == CAF_BHV_NOOP &&
+                           e.hop_actor[0] == 0 &&
+                           (e.flags & DF_INLINE_IN) != 0 &&
+                           (e.flags & (DF_INLINE_OUT | DF_SEND)) != 0;
+    L.inl[i] = echo_here ? 1u : 0u;
+    if (echo_here) {
+      L.nt[i] = 0;
+      L.any_echo = 1;
+    }
     if (!a.full && e.behavior == CAF_BHV_GEMM) atomicMin(&L.first_bad, i);
   }
   __syncthreads();
@@ -797,6 +824,14 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
     a.slots[slot].ntiles = nt;
     for (uint32_t k = 0; k < nt; ++k) a.tile2slot[(base + k) & (kTileMapCap - 1)] = slot;
     if (L.dead[i]) write_completion(a, a.slots[slot].d.req_id, CAF_E_QUIT, nullptr);
+  }
+  if (L.any_echo) {
+    // the inline echoes of the entries drained in this pass join the list
+    // of replies the drain writes itself
+    __syncthreads();
+    for (uint32_t i = t; i < cnt; i += kThreads)
+      if (L.inl[i]) L.hidx[atomicAdd(&L.nh, 1u)] = (uint16_t)i;
+    __syncthreads();
   }
   complete_hash_entries(a, L);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

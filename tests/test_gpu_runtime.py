@@ -109,6 +109,33 @@ def test_exactly_once_and_sends(sysm):
     assert after["outstanding"] == 0
 
 
+def test_pingpong_echo_lengths_and_sends(sysm):
+    """Window-1 echoes of 1..4 int32 (input and reply inline: in the ring
+    forms the drain answers them itself) and of 5 and 64 int32 (tile path),
+    with sends between them: every reply exact, one completion each."""
+    from paper_1505_07368_amd import binding as cg
+    before = sysm.stats()
+    e = sysm.spawn(cg.BHV_NOOP)
+    g = gen.rng(23)
+    nreq = nsend = 0
+    for i in range(240):
+        n = (1, 2, 3, 4, 5, 64)[i % 6]
+        x = g.integers(-2 ** 31, 2 ** 31 - 1, size=n).astype(np.int32)
+        if i % 5 == 4:
+            assert sysm.send(e, inputs=[x]) == cg.OK
+            nsend += 1
+            continue
+        st, v = sysm.request(e, inputs=[x]).result()
+        nreq += 1
+        got = v if isinstance(v, np.ndarray) else v.cpu().numpy()
+        assert st == cg.OK and np.array_equal(np.asarray(got).reshape(-1)[:n], x), (i, n)
+    assert sysm.drain(30) == cg.OK
+    after = sysm.stats()
+    assert after["duplicate_completions"] == 0
+    assert after["completions"] - before["completions"] == nreq + nsend
+    assert after["outstanding"] == 0
+
+
 def test_quit_answers_unstarted_requests(sysm):
     from paper_1505_07368_amd import binding as cg
     m = sysm.spawn(cg.BHV_MANDELBROT)
