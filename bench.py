@@ -583,8 +583,8 @@ def cpu_baseline(seeds=tuple(range(8)), single_seed=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline leg only")
     ap.add_argument("--legs", default="fp64,colour,forms,small,gemm,pipeline,serving,offload",
                     help="comma list of the legs to run beside the headline")
