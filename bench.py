@@ -410,7 +410,7 @@ def offload_leg(cg, torch, reps=3, threads=None):
 
 
 def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 << 30,
-                blocking=False):
+                blocking=False, tune=None):
     """Open-loop Poisson arrivals: 70 % Mandelbrot squares (64^2..512^2,
     max_iter 256..4096, boundary viewports, fp32), 30 % fp32 GEMM with n in
     {32..512}; admission by HBM budget and mailbox slots; latency from the
@@ -420,55 +420,19 @@ def serving_leg(cg, torch, rate, duration_s=2.0, seed=0, ring=8192, budget=32 <<
     arena, so the budget binds.  The work done is counted over the completed
     requests: Mandelbrot iterations (each message's exact count sum, from a
     closed-loop pass over the same messages before the timed run) and GEMM
-    flops (2 n^3)."""
-    from paper_1505_07368_amd import gen
+    flops (2 n^3).  tune: the autotuner's full_wgs_per_cu and max_batch."""
+    from paper_1505_07368_amd import autotune, gen
+    tune = tune or {}
     d = gen.serving_mix_arrays(seed, rate, duration_s)
     cnt = d["arrival_ns"].size
-    pool = {}
-    gg = torch.Generator(device="cuda")
-    gg.manual_seed(seed)
-    for n in gen.SERVE_GEMM_N:  # eight distinct input pairs per size
-        pool[n] = [(torch.rand(n * n, generator=gg, device="cuda") * 2 - 1,
-                    torch.rand(n * n, generator=gg, device="cuda") * 2 - 1) for _ in range(8)]
-    s = cg.System(mode="persistent", arena_bytes=budget, ring_slots=ring, blocking=blocking)
+    s = cg.System(mode="persistent", arena_bytes=budget, ring_slots=ring, blocking=blocking,
+                  max_batch=tune.get("max_batch", 1024),
+                  full_wgs_per_cu=tune.get("full_wgs_per_cu", 0))
     try:
         m = s.spawn(cg.BHV_MANDELBROT)
         gm = s.spawn(cg.BHV_GEMM)
-        margs = np.zeros(cnt, cg.NP_MANDEL)
-        margs["re_min"] = d["re_min"]
-        margs["im_min"] = d["im_min"]
-        margs["step_re"] = d["step"]
-        margs["step_im"] = d["step"]
-        margs["width"] = d["side"]
-        margs["height"] = d["side"]
-        margs["rows"] = d["side"]
-        margs["max_iter"] = d["max_iter"]
-        margs["fp"] = cg.F32
-        gargs = np.zeros(cnt, cg.NP_GEMM)
-        gargs["n"] = d["gemm_n"]
-        gargs["in_dtype"] = cg.F32
-        bufs = np.zeros(cnt * 2, cg.NP_BUF)
-        pick = np.arange(cnt) % 8
-        for n in gen.SERVE_GEMM_N:
-            sel = np.nonzero((d["gemm_n"] == n) & ~d["is_mandel"])[0]
-            for k in range(8):
-                ss = sel[pick[sel] == k]
-                bufs["data"][2 * ss] = pool[n][k][0].data_ptr()
-                bufs["data"][2 * ss + 1] = pool[n][k][1].data_ptr()
-                bufs["numel"][2 * ss] = n * n
-                bufs["numel"][2 * ss + 1] = n * n
-        bufs["dtype"] = cg.F32
-        bufs["on_device"] = 1
-        idx = np.arange(cnt, dtype=np.uint64)
-        msgs = np.zeros(cnt, cg.NP_MSG)
+        msgs, keep = autotune.mix_messages(cg, torch, d, m, gm, pool_seed=seed)
         ism = d["is_mandel"]
-        msgs["actor"] = np.where(ism, m, gm)
-        msgs["n_in"] = np.where(ism, 0, 2)
-        msgs["args"] = np.where(ism, margs.ctypes.data + idx * margs.itemsize,
-                                gargs.ctypes.data + idx * gargs.itemsize)
-        msgs["args_bytes"] = np.where(ism, margs.itemsize, gargs.itemsize)
-        msgs["in_"] = np.where(ism, 0, bufs.ctypes.data + idx * 2 * bufs.itemsize)
-        keep = (margs, gargs, bufs, pool)
         iters = mandel_work(cg, torch, s, msgs[ism], keep, d["side"][ism], window=ring // 2)
         torch.cuda.synchronize()
         # the driver's own bookkeeping never limits: the library admits
@@ -739,18 +703,23 @@ def main():
         log("[bench] pipeline")
         result["pipeline"] = pipeline_leg(cg, torch)
     if "serving" in legs:
+        mix = {}
+        if not args.no_tune:
+            log("[bench] autotune (serving mix: full-variant occupancy, max_batch)")
+            mix = autotune.tune_mix(torch, cache_path=cache)
+            tuned["serving_mix"] = mix
         serving = {}
         for rate in (1e4, 1e5, 1e6):
             # at most 2e5 arrivals per rate: above capacity the backlog, not
             # the arrival window, sets the run time
             dur = min(2.0, 2e5 / rate)
             log(f"[bench] serving {rate:g}/s for {dur:g} s")
-            serving[f"{rate:g}"] = serving_leg(cg, torch, rate, duration_s=dur)
+            serving[f"{rate:g}"] = serving_leg(cg, torch, rate, duration_s=dur, tune=mix)
         # a 64 MiB budget: admission binds on arena memory
         for blocking in (False, True):
             log(f"[bench] serving 1e5/s for 0.5 s, 64 MiB budget, blocking={blocking}")
             serving["1e5_64MiB_" + ("blocking" if blocking else "nonblocking")] = serving_leg(
-                cg, torch, 1e5, duration_s=0.5, budget=64 << 20, blocking=blocking)
+                cg, torch, 1e5, duration_s=0.5, budget=64 << 20, blocking=blocking, tune=mix)
         result["serving"] = serving
     if "offload" in legs:
         result["offload"] = offload_leg(cg, torch)

@@ -137,6 +137,11 @@ typedef struct {
   uint32_t gemm_tile;      /* GEMM output tile edge (64 or 128) for every n; 0 = per class */
   uint32_t gemm_tile_class[4]; /* tile edge for n <= 64, <= 128, <= 256, > 256;
                                   0 = default (64 up to n = 128, else 128) */
+  uint32_t full_wgs_per_cu; /* drain workgroups per compute unit while a GEMM actor
+                               exists: 0 or 2 = two (64-deep bf16 slices; suits
+                               matrix-heavy loads), 3 = three (32-deep bf16
+                               slices; more waves for escape-time tiles mixed
+                               with products, slower matrix tiles) */
 } caf_gpu_config;
 
 /* Parameter blocks (the non-buffer part of a message), one per behaviour. */

@@ -10,7 +10,9 @@ Tuned knobs:
   * Mandelbrot: pixels per work tile (512, 1024, 2048, 4096) and the drain grid
     (all workgroups resident, or half of them);
   * GEMM: output-tile edge (64 or 128) per size class (n <= 64, <= 128,
-    <= 256, > 256).
+    <= 256, > 256);
+  * a mix of escape-time tiles and products: the full drain variant's
+    workgroups per compute unit (2 or 3) and the drain batch (max_batch).
 """
 from __future__ import annotations
 
@@ -158,3 +160,84 @@ def tune_gemm(torch, mode="batched", dtype="f32", count_per_size=256, cache_path
     cache[key] = choice
     _store_cache(cache_path, cache)
     return choice
+
+
+def mix_messages(cg, torch, d, m_actor, g_actor, pool_seed=0):
+    """NP_MSG array of a serving mix (gen.serving_mix_arrays output d):
+    Mandelbrot squares to m_actor, fp32 GEMMs to g_actor with inputs from
+    eight device pairs per size.  Returns (msgs, keep): keep holds every
+    buffer the messages point into."""
+    from . import gen
+    cnt = d["arrival_ns"].size
+    pool = {}
+    gg = torch.Generator(device="cuda")
+    gg.manual_seed(pool_seed)
+    for n in gen.SERVE_GEMM_N:
+        pool[n] = [(torch.rand(n * n, generator=gg, device="cuda") * 2 - 1,
+                    torch.rand(n * n, generator=gg, device="cuda") * 2 - 1) for _ in range(8)]
+    margs = np.zeros(cnt, cg.NP_MANDEL)
+    margs["re_min"] = d["re_min"]
+    margs["im_min"] = d["im_min"]
+    margs["step_re"] = d["step"]
+    margs["step_im"] = d["step"]
+    margs["width"] = d["side"]
+    margs["height"] = d["side"]
+    margs["rows"] = d["side"]
+    margs["max_iter"] = d["max_iter"]
+    margs["fp"] = cg.F32
+    gargs = np.zeros(cnt, cg.NP_GEMM)
+    gargs["n"] = d["gemm_n"]
+    gargs["in_dtype"] = cg.F32
+    bufs = np.zeros(cnt * 2, cg.NP_BUF)
+    pick = np.arange(cnt) % 8
+    for n in gen.SERVE_GEMM_N:
+        sel = np.nonzero((d["gemm_n"] == n) & ~d["is_mandel"])[0]
+        for k in range(8):
+            ss = sel[pick[sel] == k]
+            bufs["data"][2 * ss] = pool[n][k][0].data_ptr()
+            bufs["data"][2 * ss + 1] = pool[n][k][1].data_ptr()
+            bufs["numel"][2 * ss] = n * n
+            bufs["numel"][2 * ss + 1] = n * n
+    bufs["dtype"] = cg.F32
+    bufs["on_device"] = 1
+    idx = np.arange(cnt, dtype=np.uint64)
+    msgs = np.zeros(cnt, cg.NP_MSG)
+    ism = d["is_mandel"]
+    msgs["actor"] = np.where(ism, m_actor, g_actor)
+    msgs["n_in"] = np.where(ism, 0, 2)
+    msgs["args"] = np.where(ism, margs.ctypes.data + idx * margs.itemsize,
+                            gargs.ctypes.data + idx * gargs.itemsize)
+    msgs["args_bytes"] = np.where(ism, margs.itemsize, gargs.itemsize)
+    msgs["in_"] = np.where(ism, 0, bufs.ctypes.data + idx * 2 * bufs.itemsize)
+    return msgs, (margs, gargs, bufs, pool)
+
+
+def tune_mix(torch, cache_path=None, seed=7, count=6000, window=2048, reps=3,
+             wgs=(2, 3), batches=(256, 1024)):
+    """Returns {"full_wgs_per_cu": w, "max_batch": b} for a serving mix (70 %
+    escape-time squares, 30 % fp32 products), timed closed loop through a
+    persistent system on a seeded mix of `count` messages."""
+    from . import gen
+    key = f"{_device_name(torch)}|mix|{count}|{window}"
+    cache = _load_cache(cache_path)
+    if key in cache:
+        return cache[key]
+    d = gen.serving_mix_arrays(seed, 1e5, count / 1e5)
+    best, best_t = None, float("inf")
+    for w in wgs:
+        for mb in batches:
+            s = cg.System(mode="persistent", arena_bytes=4 << 30, ring_slots=8192,
+                          max_batch=mb, full_wgs_per_cu=w)
+            try:
+                m = s.spawn(cg.BHV_MANDELBROT)
+                g = s.spawn(cg.BHV_GEMM)
+                msgs, keep = mix_messages(cg, torch, d, m, g)
+                torch.cuda.synchronize()
+                t = _time_drive(s, msgs, keep, window, reps)
+            finally:
+                s.shutdown()
+            if t < best_t:
+                best, best_t = {"full_wgs_per_cu": w, "max_batch": mb}, t
+    cache[key] = best
+    _store_cache(cache_path, cache)
+    return best

@@ -48,7 +48,7 @@ class caf_gpu_config(C.Structure):
                 ("max_batch", C.c_uint32), ("grid", C.c_uint32), ("blocking", C.c_uint32),
                 ("idle_exit_us", C.c_uint32), ("grouping", C.c_int32),
                 ("mandel_tile_px", C.c_uint32), ("gemm_tile", C.c_uint32),
-                ("gemm_tile_class", C.c_uint32 * 4)]
+                ("gemm_tile_class", C.c_uint32 * 4), ("full_wgs_per_cu", C.c_uint32)]
 
 
 class caf_mandel_args(C.Structure):
@@ -241,7 +241,7 @@ class System:
 
     def __init__(self, mode="persistent", arena_bytes=1 << 30, device=0, ring_slots=4096,
                  max_batch=1024, grid=0, blocking=True, idle_exit_us=0, grouping="lpt",
-                 mandel_tile_px=0, gemm_tile=0, gemm_tile_class=(0, 0, 0, 0)):
+                 mandel_tile_px=0, gemm_tile=0, gemm_tile_class=(0, 0, 0, 0), full_wgs_per_cu=0):
         torch = _torch()
         self.L = load()
         self.device = device
@@ -255,7 +255,7 @@ class System:
             C.c_void_p(self.dstream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
             arena_bytes, ring_slots, max_batch, grid, 1 if blocking else 0, idle_exit_us,
             GROUP_LPT if grouping == "lpt" else GROUP_FIFO, mandel_tile_px, gemm_tile,
-            (C.c_uint32 * 4)(*gemm_tile_class))
+            (C.c_uint32 * 4)(*gemm_tile_class), full_wgs_per_cu)
         torch.cuda.synchronize(device)
         h = C.c_void_p()
         rc = self.L.caf_gpu_init(C.byref(cfg), C.byref(h))

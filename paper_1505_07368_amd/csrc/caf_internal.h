@@ -159,6 +159,7 @@ struct KArgs {
   uint32_t grouping;
   uint32_t grid;
   uint32_t full;          // drain launch variant: 1 = every behaviour, 0 = all but GEMM
+  uint32_t full_wgs;      // workgroups per compute unit of the full variant (2 or 3)
 };
 
 // ---- work-tile geometry (host and device agree on it) -------------------

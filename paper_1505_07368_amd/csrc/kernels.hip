@@ -333,7 +333,7 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
 // Tiles tile .. tile + count - 1 of one message (whole workgroup).  The
 // tiles of a GEMM run as one stream (the next tile's first slice loads while
 // the current one finishes); other behaviours run tile by tile.
-template <bool kFull>
+template <bool kFull, int kBk = kBf16SliceK>
 __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t tile,
                                           uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
   if constexpr (kFull) {
@@ -342,8 +342,9 @@ __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t til
       if (d.flags & DF_BF16) {
         const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
         const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
-        if (d.tcfg == 128) gemm_bf16_tile<128>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
-        else gemm_bf16_tile<64>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+        if (d.tcfg == 128)
+          gemm_bf16_tile<128, kBk>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
+        else gemm_bf16_tile<64, kBk>(A, B, C, d.p.g.n, tile, count, (uint16_t*)smem);
       } else {
         const float* A = reinterpret_cast<const float*>(d.in0);
         const float* B = reinterpret_cast<const float*>(d.in1);
@@ -396,9 +397,11 @@ __device__ __forceinline__ void run_inline_stages(KArgsC& a, uint32_t slot, uint
   }
 }
 
-// LDS of the full variant: the largest work tile, two buffers of a bf16 GEMM
-// slice at TE = 128.  The light variant only needs the drain scratch.
-constexpr uint32_t kSmemBytes = 2 * (2 * 128 * (kBf16SliceK + 8) * 2);
+// LDS of a full variant: the largest work tile, two buffers of a bf16 GEMM
+// slice at TE = 128, for slices of bk.  The light variant only needs the
+// drain scratch.
+constexpr uint32_t smem_bytes(int bk) { return 2 * (2 * 128 * (bk + 8) * 2); }
+constexpr uint32_t kSmemBytes = smem_bytes(kBf16SliceK);
 
 // ---- one launch per message -------------------------------------------------
 
@@ -478,7 +481,7 @@ struct DrainLds {
   uint64_t d, cnt, pub, done;
   uint32_t total;
 };
-static_assert(sizeof(DrainLds) <= kSmemBytes, "drain scratch fits the tile LDS");
+static_assert(sizeof(DrainLds) <= smem_bytes(32), "drain scratch fits every tile LDS");
 constexpr uint32_t kSmemLight = (sizeof(DrainLds) + 15u) / 16u * 16u;
 
 // In-place exclusive prefix sum of v[0..count), count <= 1024, whole workgroup.
@@ -920,9 +923,9 @@ __device__ void fill_reservations_locked(KArgsC& a) {
 enum : uint32_t { CMD_IDLE = 0, CMD_TILE = 1, CMD_DRAIN = 2 };
 constexpr uint32_t kSentinels = 16;
 
-template <bool kFull>
+template <bool kFull, int kBk = kBf16SliceK>
 __device__ __forceinline__ void drain_body(KArgsC& a) {
-  __shared__ __align__(16) uint8_t smem[kFull ? kSmemBytes : kSmemLight];
+  __shared__ __align__(16) uint8_t smem[kFull ? smem_bytes(kBk) : kSmemLight];
   __shared__ __align__(16) DevSlot s_slot;
   __shared__ uint32_t s_cmd, s_exit, s_ctr, s_k, s_nop, s_cont;
   __shared__ uint64_t s_g;
@@ -1013,7 +1016,7 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         // A failed tile stops the message's other tiles; a one-tile message
         // cannot have failed before its tile runs.
         if (ntiles == 1 || ld_dev(&a.sstate[d.slot].status) == CAF_OK)
-          run_tiles<kFull>(a, d, tile, run, smem, &s_ctr);
+          run_tiles<kFull, kBk>(a, d, tile, run, smem, &s_ctr);
         __syncthreads();
         if (t == 0) s_cont = finish_tiles(a, d, ntiles, run, true) ? 1u : 0u;
         __syncthreads();
@@ -1100,10 +1103,21 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
 }
 
 // The full variant asks for two waves per SIMD (at most 256 registers,
-// accumulation registers included): two workgroups per compute unit.
+// accumulation registers included): two workgroups per compute unit, which
+// suits matrix tiles (64-deep bf16 slices, no register spills in the slice
+// loops).
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 drain_kernel_full(KArgs) {
   drain_body<true>(kargs());
+}
+
+// The same at three waves per SIMD (at most 168 registers) with 32-deep bf16
+// slices (45 KB of LDS): three workgroups per compute unit.  The matrix tiles
+// spill registers and run slower, escape-time tiles mixed with them run
+// faster (more waves to dual-issue from); a system picks one of the two.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+drain_kernel_full3(KArgs) {
+  drain_body<true, 32>(kargs());
 }
 
 // The light variant asks for five waves per SIMD (at most 96 registers).
@@ -1128,12 +1142,17 @@ const void* plain_kernel_fn(bool full) {
 }
 
 hipError_t launch_drain(const KArgs& a, hipStream_t s) {
-  if (a.full) hipLaunchKernelGGL(drain_kernel_full, dim3(a.grid), dim3(kThreads), 0, s, a);
+  if (a.full && a.full_wgs == 3)
+    hipLaunchKernelGGL(drain_kernel_full3, dim3(a.grid), dim3(kThreads), 0, s, a);
+  else if (a.full) hipLaunchKernelGGL(drain_kernel_full, dim3(a.grid), dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL(drain_kernel_light, dim3(a.grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t drain_occupancy(bool full, int* blocks_per_cu) {
+hipError_t drain_occupancy(bool full, uint32_t full_wgs, int* blocks_per_cu) {
+  if (full && full_wgs == 3)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel_full3,
+                                                        kThreads, 0);
   if (full)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel_full,
                                                         kThreads, 0);

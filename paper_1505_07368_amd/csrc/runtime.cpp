@@ -42,7 +42,7 @@
 namespace cafgpu {
 hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s);
 hipError_t launch_drain(const KArgs& a, hipStream_t s);
-hipError_t drain_occupancy(bool full, int* blocks_per_cu);
+hipError_t drain_occupancy(bool full, uint32_t full_wgs, int* blocks_per_cu);
 const void* plain_kernel_fn(bool full);
 }  // namespace cafgpu
 
@@ -1042,6 +1042,8 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   for (uint32_t t : cfg->gemm_tile_class)
     if (t != 0 && t != 64 && t != 128) return CAF_E_INVALID;
   if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT) return CAF_E_INVALID;
+  if (cfg->full_wgs_per_cu != 0 && cfg->full_wgs_per_cu != 2 && cfg->full_wgs_per_cu != 3)
+    return CAF_E_INVALID;
   if (hipSetDevice(cfg->device) != hipSuccess) return CAF_E_DEVICE;
   // once per device: the address of this device's no-alloc staging array
   if (const int st = cafgpu::offload_stage_setup(cfg->device); st != CAF_OK) return st;
@@ -1051,6 +1053,7 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   s->cap = cap;
   s->mandel_tile_px = mpx;
   s->gemm_tile = cfg->gemm_tile;
+  s->kargs.full_wgs = cfg->full_wgs_per_cu == 3 ? 3u : 2u;
   s->arena.init((uint64_t)(uintptr_t)cfg->arena, cfg->arena_bytes);
   bool ok = true;
   auto chk = [&](hipError_t e) {
@@ -1105,8 +1108,8 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   // Default grid: every workgroup resident (the kernel never needs that,
   // but it is the most work in flight).
   int occ_full = 1, occ_light = 1;
-  if (ok) chk(drain_occupancy(true, &occ_full));
-  if (ok) chk(drain_occupancy(false, &occ_light));
+  if (ok) chk(drain_occupancy(true, s->kargs.full_wgs, &occ_full));
+  if (ok) chk(drain_occupancy(false, s->kargs.full_wgs, &occ_light));
   if (occ_full < 1) occ_full = 1;
   if (occ_light < 1) occ_light = 1;
   s->grid_full = cfg->grid ? cfg->grid : (uint32_t)(cus * occ_full);

@@ -402,14 +402,14 @@ __device__ __forceinline__ void gemm_f32_tile(const float* __restrict__ A, const
 // bf16.  One call computes `count` consecutive output tiles (row-major tile
 // order) of one product.
 // k per LDS slice of the bf16 tile: long enough that a slice's matrix-core
-// work covers the next slice's global loads.
+// work covers the next slice's global loads (64); a kernel variant that keeps
+// more workgroups per compute unit uses 32, which halves the tile's LDS.
 constexpr int kBf16SliceK = 64;
 
-template <int TE>
+template <int TE, int BK = kBf16SliceK>
 __device__ __forceinline__ void gemm_bf16_tile(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
                                float* __restrict__ C, uint32_t n, uint32_t tile0,
                                uint32_t count, uint16_t* smem) {
-  constexpr int BK = kBf16SliceK;
   constexpr int LD = BK + 8;
   constexpr int WB = TE / 64;
   constexpr int QA = TE * BK / 8 / kThreads;  // 16-byte A chunks per thread

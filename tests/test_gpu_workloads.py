@@ -127,17 +127,19 @@ def _gemm_batch(cg, torch, s, sizes, dtype):
     return io
 
 
+@pytest.mark.parametrize("wgs", [2, 3])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("te", [64, 128])
-def test_gemm_batch_sampled(dtype, te):
-    """A drained batch of mixed sizes with every tile edge; one message of
-    each size (n = 512 included) checked against the FP64 oracle, every
-    output checked finite."""
+def test_gemm_batch_sampled(dtype, te, wgs):
+    """A drained batch of mixed sizes with every tile edge and both full
+    drain variants (2 workgroups per CU with 64-deep bf16 slices, 3 with
+    32-deep ones); one message of each size (n = 512 included) checked
+    against the FP64 oracle, every output checked finite."""
     import torch
     from paper_1505_07368_amd import binding as cg
     sizes = gen.gemm_sizes(0, 48)
     s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=64, max_batch=1024,
-                  gemm_tile_class=(te, te, te, te))
+                  gemm_tile_class=(te, te, te, te), full_wgs_per_cu=wgs)
     try:
         io = _gemm_batch(cg, torch, s, sizes, dtype)
     finally:
@@ -154,17 +156,20 @@ def test_gemm_batch_sampled(dtype, te):
     assert seen == {64, 128, 256, 512}
 
 
-def test_serving_mix_full():
+@pytest.mark.parametrize("wgs", [2, 3])
+def test_serving_mix_full(wgs):
     """Every request of a 0.1 s serving-mix run at 1e4 arrivals/s (about
     1,000 messages, issued as one burst through the same system
-    configuration as the serving benchmark): every Mandelbrot square
-    compared pixel for pixel, every GEMM in full (relative Frobenius error)."""
+    configuration as the serving benchmark, with either full drain variant):
+    every Mandelbrot square compared pixel for pixel, every GEMM in full
+    (relative Frobenius error)."""
     import torch
     from paper_1505_07368_amd import binding as cg
     d = gen.serving_mix_arrays(0, 1e4, 0.1)
     cnt = d["arrival_ns"].size
     assert cnt >= 900
-    s = cg.System(mode="persistent", arena_bytes=32 << 30, ring_slots=8192, blocking=False)
+    s = cg.System(mode="persistent", arena_bytes=32 << 30, ring_slots=8192, blocking=False,
+                  full_wgs_per_cu=wgs)
     try:
         m = s.spawn(cg.BHV_MANDELBROT)
         gm = s.spawn(cg.BHV_GEMM)
@@ -289,8 +294,9 @@ def test_gemm_bench_batch_full_size(dtype):
         assert err <= 1e-5, (i, got.shape[0], err)
 
 
+@pytest.mark.parametrize("wgs", [2, 3])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_gemm_ragged_runs_sampled(dtype):
+def test_gemm_ragged_runs_sampled(dtype, wgs):
     """2048 requests with ragged n (72, 100, 136, 200, 264: partial last
     k slice, both tile edges, n % 8 != 0 for 100) published in two drained
     batches, so workgroups claim several consecutive tiles of one product and
@@ -312,7 +318,8 @@ def test_gemm_ragged_runs_sampled(dtype):
         A, B, code = A.to(torch.bfloat16), B.to(torch.bfloat16), cg.BF16
     C = torch.full((total,), float("nan"), device="cuda")
     esz = A.element_size()
-    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=count, max_batch=1024)
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=count, max_batch=1024,
+                  full_wgs_per_cu=wgs)
     try:
         a = s.spawn(cg.BHV_GEMM)
         args = np.zeros(count, cg.NP_GEMM)
@@ -431,3 +438,35 @@ def test_gemm_large_single_message(dtype):
         s.shutdown()
     err = rel_fro(c, oracle.gemm(A, B, dtype))
     assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("wgs", [2, 3])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gemm_sizes_each_full_variant(dtype, wgs):
+    """Single products of n = 1 .. 512, across slice and tile boundaries of
+    both full drain variants (64- and 32-deep bf16 slices, 64- and 128-wide
+    tiles), each compared in full with the FP64 oracle."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    sizes = [1, 7, 8, 16, 24, 31, 32, 33, 40, 64, 65, 100, 128, 129, 200, 256, 264, 512]
+    with cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=64,
+                   full_wgs_per_cu=wgs) as s:
+        a = s.spawn(cg.BHV_GEMM)
+        cases = []
+        for i, n in enumerate(sizes):
+            A, B = gen.gemm_pair(900 + i, n, dtype)
+            if dtype == "bf16":
+                tA = torch.from_numpy(A.view(np.int16)).cuda().view(torch.bfloat16)
+                tB = torch.from_numpy(B.view(np.int16)).cuda().view(torch.bfloat16)
+            else:
+                tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            cases.append((n, A, B, tA, tB))
+        torch.cuda.synchronize()
+        code = cg.BF16 if dtype == "bf16" else cg.F32
+        futs = [s.request(a, cg.caf_gemm_args(n, code), inputs=[tA, tB])
+                for n, _, _, tA, tB in cases]
+        for (n, A, B, _, _), f in zip(cases, futs):
+            st, C = f.result()
+            assert st == cg.OK, (n, st)
+            err = rel_fro(C.cpu().numpy().reshape(n, n), oracle.gemm(A, B, dtype))
+            assert err <= 1e-5, (n, err)
