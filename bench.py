@@ -220,7 +220,8 @@ def _bufs_array(cg, pairs):
     return arr
 
 
-def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3, tile_class=(0, 0, 0, 0)):
+def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3, tile_class=(0, 0, 0, 0),
+             max_batch=1024, grid=0, full_wgs_per_cu=0):
     """The grouped-GEMM workload: `count` requests with n drawn from
     {64, 128, 256, 512}, entries U(-1, 1) (bf16: rounded to nearest even),
     every request with its own inputs resident in HBM."""
@@ -239,8 +240,8 @@ def gemm_leg(cg, torch, dtype, count=4096, seed=0, reps=3, tile_class=(0, 0, 0, 
     esz = A.element_size()
     flops = float((2 * sizes ** 3).sum())
     bytes_ = float((nn * (2 * esz + 4)).sum())
-    s = cg.System(mode="batched", arena_bytes=4 << 30, ring_slots=count, max_batch=1024,
-                  gemm_tile_class=tuple(tile_class))
+    s = cg.System(mode="batched", arena_bytes=4 << 30, ring_slots=count, max_batch=max_batch,
+                  grid=grid, gemm_tile_class=tuple(tile_class), full_wgs_per_cu=full_wgs_per_cu)
     try:
         a = s.spawn(cg.BHV_GEMM)
         args = np.zeros(count, cg.NP_GEMM)

@@ -247,8 +247,14 @@ __device__ __forceinline__ bool finish_tiles(KArgsC& a, const Desc& d, uint32_t 
   const uint32_t slot = d.slot;
   SlotState* ss = &a.sstate[slot];
   bool cont = false;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const bool whole = count == ntiles;
+  // Tiles of a message finished by several workgroups: each releases its
+  // part before counting it (on this chip a release writes back the
+  // workgroup's L2, so it is not free).  A run that finishes the whole
+  // message skips it: what follows -- the completion record (a system-scope
+  // release), a publication of the next stage (an agent-scope release) or
+  // that stage run by this workgroup -- orders the reply's data itself.
+  if (!whole) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const uint32_t prev =
       whole ? 0u
             : __hip_atomic_fetch_add(&ss->done, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -519,6 +525,10 @@ __device__ uint32_t block_exclusive_scan(uint32_t* v, uint32_t count, uint32_t* 
   return total;
 }
 
+// Drain ahead when fewer than this many published tiles per workgroup are
+// left unclaimed (and the mailbox holds a backlog).
+constexpr uint64_t kDrainAheadPerWg = 4;
+
 // Largest drain pass whose inline echoes the drain answers itself.
 constexpr uint32_t kDrainEchoMax = 4;
 
@@ -529,14 +539,14 @@ struct Claim {
   bool own = false;  // published by this workgroup's own drain pass
 };
 
-// Returns the published count it read (0 if it reserved nothing).
-__device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c) {
-  const uint64_t pub = ld_dev(&a.dctl->tiles_pub);
-  const uint64_t cur = ld_dev(&a.dctl->tiles_claimed);
+// Returns the published count it read (0 if it reserved nothing).  pub and
+// cur: the published count and the claim cursor, just read.
+__device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c, uint64_t pub, uint64_t cur) {
   if (cur >= pub) return 0;
   // guided self-scheduling: large chunks while plenty is published
   const uint64_t avail = pub - cur, g2 = 2ull * a.grid;
-  const uint64_t k = avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4 : avail >= 2 * g2 ? 2 : 1;
+  const uint64_t k = avail >= 16 * g2 ? 16 : avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4
+                     : avail >= 2 * g2 ? 2 : 1;
   c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   c.end = c.next + k;
@@ -945,7 +955,19 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
     if (t == 0) {
       uint32_t cmd = CMD_IDLE;
       uint64_t pub = 0;
-      if (c.next == c.end) pub = reserve(a, c);
+      if (c.next == c.end) {
+        const uint64_t pub0 = ld_dev(&a.dctl->tiles_pub);
+        const uint64_t cur0 = ld_dev(&a.dctl->tiles_claimed);
+        // Drain ahead: while the mailbox holds more than one pass and the
+        // published tiles nobody has claimed yet run low, this workgroup
+        // takes the next pass now (one attempt at the lock), so that the
+        // others are not left without tiles while it is drained.
+        if (cur0 + kDrainAheadPerWg * a.grid > pub0 && ld_dev(&a.dctl->backlog) != 0 &&
+            lock_drain(a, false))
+          cmd = CMD_DRAIN;
+        else
+          pub = reserve(a, c, pub0, cur0);
+      }
       if (c.next < c.end && c.own) {
         // An index of this workgroup's own drain pass: published, its slot
         // and tile map entry are this workgroup's writes, and the pass's
