@@ -377,7 +377,8 @@ int caf_offload_mandel(caf_gpu_system* sys, caf_actor gpu_actor, const caf_mande
  * device, held from the first caf_gpu_init on that device until the
  * process ends.  The call allocates no device or pinned host memory (no
  * hipMalloc, hipHostMalloc or hipFree, no arena bytes: the replies go to
- * the array) and keeps its request table on the stack.
+ * the array), keeps its request table on the stack, and takes its requests'
+ * futures from the system's pool (filled by caf_gpu_init).
  * Limits: gpu_rows * width * 2 <= CAF_OFFLOAD_NOALLOC_STAGE_BYTES and
  * gpu_rows <= CAF_OFFLOAD_NOALLOC_MAX_ROWS, else CAF_E_INVALID; a CPU share
  * (gpu_rows < height) needs the system's CPU actors to be running with

@@ -410,6 +410,10 @@ void ensure_drain(caf_gpu_system* s, bool only_if_pending) {
   if (s->held.load(std::memory_order_acquire)) return;
   if (drain_running(s)) return;  // fast path, no lock
   std::lock_guard<std::mutex> g(s->launch_mu);
+  // again under the lock: caf_gpu_hold sets the flag under it, so a caller
+  // that passed the check above before a hold, and finds work pending only
+  // because the held messages arrived meanwhile, launches nothing
+  if (s->held.load(std::memory_order_acquire)) return;
   if (drain_running(s)) return;
   if (only_if_pending &&
       __atomic_load_n(&s->hctl->drained, __ATOMIC_ACQUIRE) >=
@@ -1132,6 +1136,19 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
     return CAF_E_DEVICE;
   }
   for (uint32_t i = 0; i < cap; ++i) s->free_slots.push_back(cap - 1 - i);
+  // Futures for the first requests, so that a request rarely allocates one
+  // (caf_offload_mandel_noalloc's requests come from here).
+  try {
+    for (uint32_t i = 0; i < std::min(cap, 1024u); ++i) {
+      caf_future* f = new caf_future();
+      f->pooled = true;
+      s->all_futs.push_back(f);
+      s->fut_pool.push_back(f);
+    }
+  } catch (...) {
+    caf_gpu_shutdown(s);
+    return CAF_E_OVERLOAD;
+  }
   KArgs& a = s->kargs;
   a.hctl = s->hctl;
   a.hring = s->hring;
@@ -1293,7 +1310,11 @@ int caf_gpu_quit(caf_gpu_system* s, caf_actor actor, uint32_t /*exit_reason*/) {
 int caf_gpu_hold(caf_gpu_system* s, int32_t hold) {
   if (!s) return CAF_E_INVALID;
   if (s->plain()) return CAF_E_INVALID;  // plain forms launch at submit time
-  s->held.store(hold != 0, std::memory_order_release);
+  {
+    // under the launch lock: no launch decided before the hold starts after it
+    std::lock_guard<std::mutex> g(s->launch_mu);
+    s->held.store(hold != 0, std::memory_order_release);
+  }
   if (!hold) ensure_drain(s, true);  // one launch for everything that waited
   return CAF_OK;
 }

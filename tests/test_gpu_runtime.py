@@ -617,3 +617,38 @@ def test_hold_collects_one_batch(mode):
         assert s.stats()["drain_launches"] == before + 1
     with cg.System(mode="plain", arena_bytes=16 << 20) as p:
         assert p.hold(True) == cg.E_INVALID
+
+
+def test_shutdown_while_held_answers_quit():
+    """Requests still held in the mailbox at shutdown never ran: each
+    future resolves once, with CAF_E_QUIT.  Each round follows a busy
+    persistent system, the condition under which a poller that had checked
+    the hold just before it started once launched a drain for the held
+    messages (the hold is now set and checked under the launch lock)."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    for rnd in range(6):
+        with cg.System(mode="persistent", arena_bytes=64 << 20, ring_slots=256,
+                       idle_exit_us=50) as s0:
+            g = s0.spawn(cg.BHV_GEMM)
+            A, B = gen.gemm_pair(710 + rnd, 96)
+            dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            torch.cuda.synchronize()
+            for f in [s0.request(g, cg.caf_gemm_args(96, cg.F32), inputs=[dA, dB])
+                      for _ in range(8)]:
+                assert f.result()[0] == cg.OK
+        s = cg.System(mode="batched", arena_bytes=16 << 20, ring_slots=64)
+        e = s.spawn(cg.BHV_NOOP)
+        st, v = s.request(e, inputs=[np.array([5], np.int32)]).result()
+        assert st == cg.OK and v.tolist() == [5]
+        assert s.drain() == cg.OK
+        s.drain_kernel_ms()
+        assert s.hold(True) == cg.OK
+        futs = [s.request(e, inputs=[np.array([i], np.int32)]) for i in range(10)]
+        s.shutdown()
+        got = []
+        for f in futs:
+            st, _ = f.wait(5.0)
+            got.append(st)
+            f.release()
+        assert got == [cg.E_QUIT] * 10, (rnd, got)
