@@ -16,8 +16,12 @@
 // yet stays at the head of the driver's queue -- later messages keep their
 // order behind it -- and is retried after the next replies are harvested,
 // which frees their slots and arena buffers: messages are admitted as room
-// frees up, and the open-loop latency includes that wait.  With a
-// non-blocking system, a refused request is final (status CAF_E_OVERLOAD).
+// frees up, and the open-loop latency includes that wait.  The next stage
+// of a host-mediated chain waits the same way, ahead of new messages; if
+// stages wait while none of the driver's own requests is in flight (the
+// arena is held by the waiting chains' replies, so no wait could end), the
+// oldest waiting chain is refused (CAF_E_OVERLOAD) and its reply released.
+// With a non-blocking system, a refused request is final (CAF_E_OVERLOAD).
 //
 // Replies are harvested through a completion queue that the poller thread
 // fills with the tags of resolved requests, so harvesting costs O(1) per
@@ -80,6 +84,7 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
   for (uint32_t k = 0; k < window; ++k) free_tags.push_back(window - 1 - k);
   int first_err = CAF_OK;
   uint64_t next = 0, done = 0;
+  uint64_t live = 0;  // this driver's requests issued and not yet harvested
   const int64_t t_start = now_ns();
 
   auto fail = [&](uint64_t i, int st) {
@@ -104,6 +109,7 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
       return true;
     }
     free_tags.pop_back();
+    ++live;
     Pending& p = pend[tag];
     p = Pending();
     p.f = f;
@@ -112,8 +118,42 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
     return true;
   };
 
+  // Sends the next chain stage of tag k (its input: the previous stage's
+  // reply); false if it does not fit yet (blocking system only).
+  auto issue_hop = [&](uint32_t k) -> bool {
+    Pending& p = pend[k];
+    const caf_msg& m = msgs[p.idx];
+    const bool final_here = p.stage == chain_hops;
+    caf_future* f = nullptr;
+    const int st = cafgpu_request_tagged(sys, hop_actor[p.stage - 1], m.sender, &p.shape,
+                                         sizeof p.shape, &p.in, 1,
+                                         (final_here && m.out.data) ? &m.out : nullptr, 0, &f,
+                                         &q, k, wait_for_room);
+    if (st == kTryLater) return false;
+    if (st == CAF_OK) {
+      p.f = f;
+      ++live;
+      return true;
+    }
+    caf_future_release(p.prev);
+    p.prev = nullptr;
+    fail(p.idx, st);
+    free_tags.push_back(k);
+    return true;
+  };
+  // chain stages waiting for room, in the order their inputs arrived (a
+  // ring: at most `window` tags wait at once)
+  std::vector<uint32_t> hop_wait;
+  uint64_t hop_head = 0, hop_tail = 0;
+  try {
+    hop_wait.resize(chain_hops ? window : 1);
+  } catch (...) {
+    return CAF_E_OVERLOAD;
+  }
+
   // Handles the resolved request of tag k.
   auto on_reply = [&](uint32_t k) {
+    --live;
     Pending& p = pend[k];
     caf_buf res{};
     int32_t rs = CAF_OK;
@@ -123,27 +163,14 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
       p.prev = nullptr;
     }
     if (rs == CAF_OK && p.stage < chain_hops) {
-      const caf_msg& m = msgs[p.idx];
       const uint32_t n = (uint32_t)std::llround(std::sqrt((double)res.numel));
       p.prev = p.f;
       p.in = res;
       p.shape.rows = n;
       p.shape.cols = n;
       p.stage += 1;
-      const bool final_here = p.stage == chain_hops;
-      caf_future* f = nullptr;
-      const int st = cafgpu_request_tagged(sys, hop_actor[p.stage - 1], m.sender, &p.shape,
-                                           sizeof p.shape, &p.in, 1,
-                                           (final_here && m.out.data) ? &m.out : nullptr, 0, &f,
-                                           &q, k);
-      if (st == CAF_OK) {
-        p.f = f;
-        return;
-      }
-      caf_future_release(p.prev);
-      p.prev = nullptr;
-      fail(p.idx, st);
-      free_tags.push_back(k);
+      // stages already waiting go first, so chains keep their order
+      if (hop_head < hop_tail || !issue_hop(k)) hop_wait[hop_tail++ % window] = k;
       return;
     }
     if (status) status[p.idx] = rs;
@@ -168,6 +195,24 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
 
   while (done < count) {
     bool issued = false;
+    // chain stages that did not fit go before any new message
+    while (hop_head < hop_tail && issue_hop(hop_wait[hop_head % window])) {
+      ++hop_head;
+      issued = true;
+    }
+    if (hop_head < hop_tail && live == 0) {
+      // Stages wait and none of this driver's requests is in flight to free
+      // room: the memory is held by the waiting chains' own replies (or by
+      // others), so waiting could never end.  The oldest waiting chain is
+      // refused and its reply released, which lets the others go on.
+      const uint32_t k = hop_wait[hop_head++ % window];
+      Pending& p = pend[k];
+      caf_future_release(p.prev);
+      p.prev = nullptr;
+      fail(p.idx, CAF_E_OVERLOAD);
+      free_tags.push_back(k);
+      issued = true;
+    }
     // messages [next, due) may be issued now, in order
     uint64_t due = count;
     if (arrival_ns) {
@@ -175,7 +220,7 @@ extern "C" int caf_gpu_drive(caf_gpu_system* sys, const caf_msg* msgs, uint64_t 
       due = next;
       while (due < count && arrival_ns[due] <= now) ++due;
     }
-    while (next < due && !free_tags.empty()) {
+    while (next < due && !free_tags.empty() && hop_head == hop_tail) {
       if (!issue_first(next, arrival_ns ? t_start + arrival_ns[next] : -1)) break;
       ++next;
       issued = true;

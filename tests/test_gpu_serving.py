@@ -148,3 +148,42 @@ def test_driver_blocking_admission_small_budget():
     assert (lat > 0).all()
     torch.cuda.synchronize()
     _check(cases, _oracle(cases), [o.cpu().numpy() for o in outs])
+
+
+@pytest.mark.parametrize("arena_kib", [3072, 512])
+def test_driver_host_chains_under_blocking_budget(arena_kib):
+    """Host-mediated chains GEMM (n = 128) -> tanh -> row sum through the
+    native driver with a blocking system and 32 chains in flight.  With
+    3 MiB the first stages' replies (2 MiB at most) leave room for the next
+    stages, which wait in the driver, in order, until earlier replies are
+    released: every chain completes.  With 512 KiB the first stages' replies
+    fill the arena and no next stage could ever be admitted: the driver
+    refuses the oldest waiting chain (CAF_E_OVERLOAD) and releases its reply
+    rather than waiting forever.  Every completed chain equals the oracle's."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    n, chains = 128, 48
+    inputs, outs = [], []
+    for c in range(chains):
+        A, B = gen.gemm_pair(3000 + c, n)
+        inputs.append((A, B, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()))
+        outs.append(torch.zeros(n, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    with cg.System(mode="batched", arena_bytes=arena_kib << 10, ring_slots=64,
+                   blocking=True) as s:
+        rs = s.spawn(cg.BHV_ROWSUM, n=n)
+        th = s.spawn(cg.BHV_TANH, n=n)
+        gm = s.spawn(cg.BHV_GEMM, n=n)
+        msgs = [{"actor": gm, "args": cg.caf_gemm_args(n, cg.F32), "inputs": [At, Bt], "out": o}
+                for (_, _, At, Bt), o in zip(inputs, outs)]
+        rc, lat, st, _ = s.drive(msgs, window=32, chain_hops=2, hop_actors=(th, rs))
+        assert rc == cg.OK and ((st == cg.OK) | (st == cg.E_OVERLOAD)).all(), np.unique(st)
+        stats = s.stats()
+    assert stats["arena_peak"] <= arena_kib << 10
+    if arena_kib == 3072:
+        assert (st == cg.OK).all()
+    assert (st == cg.OK).sum() > 0
+    torch.cuda.synchronize()
+    for (A, B, _, _), o, sti in zip(inputs, outs, st):
+        if sti == cg.OK:
+            assert rel_fro(o.cpu().numpy(), oracle.chain(A, B)) <= 1e-5
