@@ -648,7 +648,19 @@ def main():
                 result["roofline"]["of_interior"] = round(
                     result["roofline"]["achieved"] * 1e12 / ops_s, 4)
     legs = set() if args.quick else set(args.legs.split(","))
-    if "fp64" in legs:
+
+    def run_leg(name, fn):
+        """Runs one leg beside the headline; a failure is recorded in its
+        place (with the traceback on stderr) so the headline line still
+        prints."""
+        try:
+            fn()
+        except Exception as e:  # noqa: BLE001 -- any leg failure is reported, not fatal
+            import traceback
+            traceback.print_exc()
+            result[name] = {"error": f"{type(e).__name__}: {e}"}
+
+    def leg_fp64():
         log("[bench] batched fp64")
         f64 = mandel_leg(cg, torch, "batched", cg.F64, max(2, args.steps // 2), 1, seeds, True,
                          tune=tuned.get("mandel"))
@@ -658,7 +670,8 @@ def main():
             result["fp64"]["alu_frac"] = round(
                 f64["iters_per_step"] * max(2, args.steps // 2) * OPS_PER_ITER
                 / (f64["kernel_ms_total"] * 1e-3) / VALU_PEAK["f64"], 4)
-    if "colour" in legs:
+
+    def leg_colour():
         # the same batch through an actor spawned with a 256-entry palette:
         # the colour map is fused into the tile's store (4-byte pixels)
         log("[bench] batched fp32, colour replies")
@@ -670,14 +683,17 @@ def main():
                          tune=tuned.get("mandel"), palette=pal)
         result["colour"] = {k: col[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
         result["colour"]["vs_counts"] = round(col["giter_s"] / result["value"], 4)
-    if "forms" in legs:
+
+    def leg_forms():
         for mode in ("persistent", "plain", "plain_graph"):
             log(f"[bench] {mode} fp32")
             r = mandel_leg(cg, torch, mode, cg.F32, max(2, args.steps // 2), 1, seeds,
                            tune=tuned.get("mandel") if mode != "plain" else None)
             result[mode] = {k: r[k] for k in ("giter_s", "msgs_per_s", "p50_us", "p99_us")}
-    if "small" in legs:
+
+    def leg_small():
         small = {}
+        result["small_messages"] = small
         for kind, count in (("echo", 10000), ("mandel64", 4096), ("gemm64", 4096),
                             ("hash", 4096)):
             for window in ((1, 64, 1024) if kind == "echo" else (256,)):
@@ -690,26 +706,28 @@ def main():
                 row["batched_over_plain"] = round(
                     row["batched"]["msgs_per_s"] / row["plain"]["msgs_per_s"], 2)
                 small[f"{kind}_w{window}"] = row
-        result["small_messages"] = small
-    if "gemm" in legs:
-        for dt in args.gemm_dtypes.split(","):
-            tc = (0, 0, 0, 0)
-            if not args.no_tune:
-                log(f"[bench] autotune gemm {dt}")
-                tc = autotune.tune_gemm(torch, dtype=dt, cache_path=cache)
-                tuned[f"gemm_{dt}_tile_class"] = tc
-            log(f"[bench] gemm batch {dt}")
-            result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt, tile_class=tc)
-    if "pipeline" in legs:
+
+    def leg_gemm(dt):
+        tc = (0, 0, 0, 0)
+        if not args.no_tune:
+            log(f"[bench] autotune gemm {dt}")
+            tc = autotune.tune_gemm(torch, dtype=dt, cache_path=cache)
+            tuned[f"gemm_{dt}_tile_class"] = tc
+        log(f"[bench] gemm batch {dt}")
+        result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt, tile_class=tc)
+
+    def leg_pipeline():
         log("[bench] pipeline")
         result["pipeline"] = pipeline_leg(cg, torch)
-    if "serving" in legs:
+
+    def leg_serving():
         mix = {}
         if not args.no_tune:
             log("[bench] autotune (serving mix: full-variant occupancy, max_batch)")
             mix = autotune.tune_mix(torch, cache_path=cache)
             tuned["serving_mix"] = mix
         serving = {}
+        result["serving"] = serving
         for rate in (1e4, 1e5, 1e6):
             # at most 2e5 arrivals per rate: above capacity the backlog, not
             # the arrival window, sets the run time
@@ -721,13 +739,28 @@ def main():
             log(f"[bench] serving 1e5/s for 0.5 s, 64 MiB budget, blocking={blocking}")
             serving["1e5_64MiB_" + ("blocking" if blocking else "nonblocking")] = serving_leg(
                 cg, torch, 1e5, duration_s=0.5, budget=64 << 20, blocking=blocking, tune=mix)
-        result["serving"] = serving
-    if "offload" in legs:
+
+    def leg_offload():
         result["offload"] = offload_leg(cg, torch)
-    result["tuned"] = tuned
-    if not args.no_cpu:
+
+    def leg_cpu():
         log("[bench] cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline()
+
+    for name, fn in (("fp64", leg_fp64), ("colour", leg_colour), ("forms", leg_forms),
+                     ("small", leg_small)):
+        if name in legs:
+            run_leg(name, fn)
+    if "gemm" in legs:
+        for dt in args.gemm_dtypes.split(","):
+            run_leg(f"gemm_{dt}", lambda dt=dt: leg_gemm(dt))
+    for name, fn in (("pipeline", leg_pipeline), ("serving", leg_serving),
+                     ("offload", leg_offload)):
+        if name in legs:
+            run_leg(name, fn)
+    result["tuned"] = tuned
+    if not args.no_cpu:
+        run_leg("cpu_baseline", leg_cpu)
     print(json.dumps(result), flush=True)
 
 
