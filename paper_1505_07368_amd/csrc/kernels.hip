@@ -305,8 +305,8 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
                          uint32_t* lds_ctr) {
   switch (d.behavior) {
     case CAF_BHV_MANDELBROT:
-      if (d.flags & DF_FP64) mandel_tile<double>(d, tile, lds_ctr);
-      else mandel_tile<float>(d, tile, lds_ctr);
+      if (d.flags & DF_FP64) mandel_tile<double>(d, tile, 1u, lds_ctr);
+      else mandel_tile<float>(d, tile, 1u, lds_ctr);
       break;
     case CAF_BHV_GEMM:
       // never reached: products run through run_tiles (one call site keeps
@@ -338,7 +338,8 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
 
 // Tiles tile .. tile + count - 1 of one message (whole workgroup).  The
 // tiles of a GEMM run as one stream (the next tile's first slice loads while
-// the current one finishes); other behaviours run tile by tile.
+// the current one finishes), those of a Mandelbrot message as one range of
+// pixel blocks; other behaviours run tile by tile.
 template <bool kFull, int kBk = kBf16SliceK>
 __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t tile,
                                           uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
@@ -359,6 +360,11 @@ __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t til
       }
       return;
     }
+  }
+  if (d.behavior == CAF_BHV_MANDELBROT) {
+    if (d.flags & DF_FP64) mandel_tile<double>(d, tile, count, lds_ctr);
+    else mandel_tile<float>(d, tile, count, lds_ctr);
+    return;
   }
   for (uint32_t i = 0; i < count; ++i) {
     if (i) __syncthreads();
@@ -543,8 +549,11 @@ struct Claim {
 // cur: the published count and the claim cursor, just read.
 __device__ __forceinline__ uint64_t reserve(KArgsC& a, Claim& c, uint64_t pub, uint64_t cur) {
   if (cur >= pub) return 0;
-  // guided self-scheduling: large chunks while plenty is published
-  const uint64_t avail = pub - cur, g2 = 2ull * a.grid;
+  // Guided self-scheduling: large chunks while plenty is published.  The
+  // full variant takes twice as large chunks: a run that covers a whole
+  // product skips its release, while escape-time tiles, whose cost is not
+  // known in advance, need the smaller chunks to end a batch evenly.
+  const uint64_t avail = pub - cur, g2 = (a.full ? 1ull : 2ull) * a.grid;
   const uint64_t k = avail >= 16 * g2 ? 16 : avail >= 8 * g2 ? 8 : avail >= 4 * g2 ? 4
                      : avail >= 2 * g2 ? 2 : 1;
   c.next = __hip_atomic_fetch_add(&a.dctl->tiles_claimed, k, __ATOMIC_RELAXED,
@@ -944,7 +953,10 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
   __shared__ uint64_t s_seen_pub, s_seen_drained, s_still_since;
   const uint32_t t = threadIdx.x;
   uint64_t last_work = now_ticks();
-  uint32_t idle_rounds = 0;
+  // At the start of a launch only the sentinels try the drain lock: every
+  // workgroup trying it at once is a storm of compare-and-swaps (each with
+  // its fences) that delays the first drain pass by microseconds.
+  uint32_t idle_rounds = blockIdx.x < kSentinels ? 0u : 1u;
   Claim c;  // thread 0's reservation
   if (t == 0) {
     s_seen_pub = ~0ull;
@@ -1032,9 +1044,11 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         }
         const uint32_t ntiles = __builtin_amdgcn_readfirstlane(s_slot.ntiles);
         const uint32_t tile = __builtin_amdgcn_readfirstlane((uint32_t)(g - s_slot.tile_base));
-        // The claimed indices that follow and still belong to this GEMM
-        // message run together, with one lookup and one completion count.
-        const uint32_t run = (kFull && d.behavior == CAF_BHV_GEMM) ? min(nk - j, ntiles - tile) : 1u;
+        // The claimed indices that follow and still belong to this GEMM or
+        // Mandelbrot message run together, with one lookup and one
+        // completion count.
+        const bool runs = (kFull && d.behavior == CAF_BHV_GEMM) || d.behavior == CAF_BHV_MANDELBROT;
+        const uint32_t run = runs ? min(nk - j, ntiles - tile) : 1u;
         // A failed tile stops the message's other tiles; a one-tile message
         // cannot have failed before its tile runs.
         if (ntiles == 1 || ld_dev(&a.sstate[d.slot].status) == CAF_OK)

@@ -145,8 +145,12 @@ __device__ __forceinline__ void escape_count(const T (&cr_in)[P], const T (&ci_i
   }
 }
 
+// Tiles tile .. tile + count - 1 of one message: their blocks form one
+// range that the four waves share, so a claimed run of small tiles keeps
+// every wave busy while the tiles stay small enough to even out the end of
+// a batch.
 template <typename T>
-__device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
+__device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t count, uint32_t* lds_ctr) {
   // pixels per lane: four in float (the loop dual-issues), two in double
   constexpr int P = sizeof(T) == 4 ? 4 : 2;
   T re_min, im_min, step_re, step_im;
@@ -173,7 +177,7 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t* lds_ctr) {
   const uint32_t nb = mandel_blocks(width, rows);
   const uint32_t bpt = d.tcfg / 64;
   const uint32_t b0 = tile * bpt;
-  const uint32_t b1 = min(nb, b0 + bpt);
+  const uint32_t b1 = min(nb, b0 + bpt * count);
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) *lds_ctr = 0;
   __syncthreads();
