@@ -492,6 +492,11 @@ struct DrainLds {
   uint32_t wave_sum[4];
   uint64_t d, cnt, pub, done;
   uint32_t total;
+  // set by a sentinel before its drain pass: the launch may retire if the
+  // pass finds the mailbox empty and the drained count still equal to this
+  // (checked under the drain lock)
+  uint32_t retire_ok;
+  uint64_t retire_drained;
 };
 static_assert(sizeof(DrainLds) <= smem_bytes(32), "drain scratch fits every tile LDS");
 constexpr uint32_t kSmemLight = (sizeof(DrainLds) + 15u) / 16u * 16u;
@@ -684,7 +689,18 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
   __syncthreads();
   uint32_t cnt = (uint32_t)L.cnt;
   if (cnt == 0) {
-    if (t == 0) unlock_drain(a);
+    if (t == 0) {
+      // An idle batched launch retires here, holding the drain lock: no other
+      // pass can be publishing, and the tail was just read.  Every workgroup
+      // of it leaves once it holds no work (claimed tiles are finished
+      // first), and the host starts a new launch when messages arrive.
+      if (L.retire_ok && L.d == L.retire_drained && ld_dev(&a.dctl->tiles_claimed) >= L.pub) {
+        const uint32_t par = a.gen & 1u;
+        st_dev(&a.dctl->retiring[par], a.gen);
+        st_sys_rel(&a.hctl->retiring[par], a.gen);
+      }
+      unlock_drain(a);
+    }
     return false;
   }
   // Copy the entries into their device slots.
@@ -950,7 +966,8 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
   __shared__ uint64_t s_g;
   // sentinel: the published and drained counts last seen, and since when
   // they have not moved (thread 0; kept in LDS, not in registers)
-  __shared__ uint64_t s_seen_pub, s_seen_drained, s_still_since;
+  __shared__ uint64_t s_seen_drained, s_still_since;
+  __shared__ uint32_t s_retire_ok;
   const uint32_t t = threadIdx.x;
   uint64_t last_work = now_ticks();
   // At the start of a launch only the sentinels try the drain lock: every
@@ -959,9 +976,9 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
   uint32_t idle_rounds = blockIdx.x < kSentinels ? 0u : 1u;
   Claim c;  // thread 0's reservation
   if (t == 0) {
-    s_seen_pub = ~0ull;
     s_seen_drained = ~0ull;
     s_still_since = last_work;
+    s_retire_ok = 0;
   }
   for (;;) {
     if (t == 0) {
@@ -1064,7 +1081,12 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
       continue;
     }
     if (cmd == CMD_DRAIN) {
-      const bool got = drain_once<kFull>(a, *reinterpret_cast<DrainLds*>(smem), c);
+      DrainLds& L = *reinterpret_cast<DrainLds*>(smem);
+      if (t == 0) {
+        L.retire_ok = s_retire_ok;
+        L.retire_drained = s_seen_drained;
+      }
+      const bool got = drain_once<kFull>(a, L, c);
       __syncthreads();
       if (got) {
         last_work = now_ticks();
@@ -1090,28 +1112,23 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         }
       } else if (leaving) {
         ex = 1;
-      } else if (blockIdx.x < kSentinels && now_ticks() - last_work > a.idle_ticks) {
-        // The system counts as idle once neither the published tile count
-        // nor the drained count has moved for the linger time (this
-        // sentinel's own last work says nothing about the others').
-        const uint64_t pubv = ld_dev(&a.dctl->tiles_pub);
-        const uint64_t drv = ld_dev_acq(&a.dctl->drained);
+      } else if (blockIdx.x < kSentinels) {
+        // The system counts as idle once no drain pass has taken a message
+        // for the linger time while this sentinel had no work (its own last
+        // work says nothing about the others'; every published tile comes
+        // from such a pass, except fillers, which carry no work).  Then its
+        // next drain pass retires the launch if it finds the mailbox empty
+        // and the drained count unchanged (batched mode lingers a few tens
+        // of microseconds, persistent mode much longer).
+        const uint64_t drv = ld_dev(&a.dctl->drained);
         const uint64_t now = now_ticks();
-        if (pubv != s_seen_pub || drv != s_seen_drained) {
-          s_seen_pub = pubv;
+        if (drv != s_seen_drained || idle_rounds == 0) {
           s_seen_drained = drv;
           s_still_since = now;
-        } else if (now - s_still_since > a.idle_ticks &&
-                   ld_dev(&a.dctl->tiles_claimed) >= pubv && ld_dev(&a.dctl->drain_lock) == 0 &&
-                   ld_sys_acq(&a.hctl->tail) == drv) {
-          // Idle long enough with an empty mailbox: retire this launch.
-          // Every workgroup of it leaves once it holds no work (claimed
-          // tiles are finished first), and the host starts a new launch when
-          // messages arrive.  Batched mode lingers a few tens of
-          // microseconds, persistent mode much longer.
-          st_dev(&a.dctl->retiring[par], a.gen);
-          st_sys_rel(&a.hctl->retiring[par], a.gen);
-          ex = 1;
+          s_retire_ok = 0;
+        } else {
+          s_retire_ok = now - s_still_since > a.idle_ticks &&
+                        ld_dev(&a.dctl->tiles_claimed) >= ld_dev(&a.dctl->tiles_pub) ? 1u : 0u;
         }
       }
       s_exit = ex;
