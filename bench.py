@@ -119,18 +119,22 @@ def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tu
         # marshalling is not part of a step)
         timed = a if palette is None else s.spawn(cg.BHV_MANDELBROT, palette=palette)
         arr["actor"] = timed
+        step = cg.PreparedDrive(s, arr, window=len(arr))
         for _ in range(warmup):
-            cg.drive_array(s, arr, (arr_args,), window=len(arr))
+            step()
         s.drain_kernel_ms()  # reset the launch timers
         torch.cuda.synchronize()
+        lats, step_s, bad = [], [], 0
         t0 = time.perf_counter()
-        lats, step_s = [], []
+        t = t0
         for _ in range(steps):
-            t = time.perf_counter()
-            rc, lat, st, _ = cg.drive_array(s, arr, (arr_args,), window=len(arr))
-            step_s.append(time.perf_counter() - t)
-            assert rc == cg.OK and (st == cg.OK).all()
-            lats.append(lat)
+            rc = step()
+            t1 = time.perf_counter()
+            step_s.append(t1 - t)
+            t = t1
+            bad += rc != cg.OK or not (step.st == cg.OK).all()
+            lats.append(step.lat.copy())
+        assert bad == 0
         if mode == "persistent":
             torch.cuda.current_stream().synchronize()
         else:
@@ -151,9 +155,9 @@ def mandel_leg(cg, torch, mode, fp, steps, warmup, seeds, timed_kernel=False, tu
             ds = []
             for _ in range(dispersion_reps):
                 t = time.perf_counter()
-                rc, _, st, _ = cg.drive_array(s, arr, (arr_args,), window=len(arr))
+                rc = step()
                 ds.append(time.perf_counter() - t)
-                assert rc == cg.OK and (st == cg.OK).all()
+                assert rc == cg.OK and (step.st == cg.OK).all()
             ds = np.asarray(ds)
             g = iters / ds / 1e9
             out["dispersion"] = {"reps": dispersion_reps, "step_ms_mean": float(ds.mean() * 1e3),

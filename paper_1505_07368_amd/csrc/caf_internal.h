@@ -66,7 +66,7 @@ struct alignas(16) Desc {
       uint32_t pad[4];
       uint32_t width, row0, rows, max_iter;
     } m32;
-    struct { uint32_t n; } g;
+    struct { uint32_t n, unit; } g;  // unit: output tiles per work unit (0: 1)
     struct { uint32_t rows, cols; } s;
     struct { uint64_t x; } h;
     uint8_t raw[48];
@@ -170,6 +170,23 @@ __host__ __device__ inline uint32_t mandel_blocks(uint32_t width, uint32_t rows)
   return bw * bh;
 }
 
+// A product's output tiles (tcfg x tcfg blocks of C) and the work units
+// they are claimed and completed in: `unit` consecutive tiles in row-major
+// tile order.  A unit that covers a whole product completes it without the
+// shared tile count and the release before it; units of several tiles
+// therefore suit products whose tiles are short next to that release.
+__host__ __device__ inline uint32_t gemm_tiles(const Desc& d) {
+  const uint32_t t = (d.p.g.n + d.tcfg - 1) / d.tcfg;
+  return t * t;
+}
+__host__ __device__ inline uint32_t gemm_unit(const Desc& d) { return d.p.g.unit ? d.p.g.unit : 1u; }
+// bf16 products: four tiles per unit.  A 128 x 128 bf16 tile is short next
+// to the agent-scope release (an L2 writeback) that a partial run needs, so
+// a product of up to four tiles completes whole; fp32 tiles are long
+// enough that single tiles end a batch more evenly.
+constexpr uint32_t kGemmUnitBf16 = 4;
+
+// Claimable work units of a message (the drain's "tiles").
 __host__ __device__ inline uint32_t desc_ntiles(const Desc& d) {
   switch (d.behavior) {
     case CAF_BHV_MANDELBROT: {
@@ -179,9 +196,8 @@ __host__ __device__ inline uint32_t desc_ntiles(const Desc& d) {
       return nb == 0 ? 1u : (nb + bpt - 1) / bpt;  // an empty tile still replies
     }
     case CAF_BHV_GEMM: {
-      uint32_t te = d.tcfg;
-      uint32_t t = (d.p.g.n + te - 1) / te;
-      return t * t;
+      const uint32_t u = gemm_unit(d);
+      return (gemm_tiles(d) + u - 1) / u;
     }
     case CAF_BHV_TANH: {
       uint64_t ne = (uint64_t)d.p.s.rows * d.p.s.cols;

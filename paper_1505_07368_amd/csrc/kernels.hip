@@ -336,8 +336,9 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
   }
 }
 
-// Tiles tile .. tile + count - 1 of one message (whole workgroup).  The
-// tiles of a GEMM run as one stream (the next tile's first slice loads while
+// Tiles tile .. tile + count - 1 of one message (whole workgroup; for a GEMM
+// these are work units, each `unit` output tiles).  The tiles of a GEMM run
+// as one stream (the next tile's first slice loads while
 // the current one finishes), those of a Mandelbrot message as one range of
 // pixel blocks; other behaviours run tile by tile.
 template <bool kFull, int kBk = kBf16SliceK>
@@ -345,6 +346,11 @@ __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t til
                                           uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
   if constexpr (kFull) {
     if (d.behavior == CAF_BHV_GEMM) {
+      // work units -> output tiles
+      const uint32_t u = gemm_unit(d), all = gemm_tiles(d);
+      const uint32_t t0 = tile * u;
+      count = min(t0 + count * u, all) - t0;
+      tile = t0;
       float* C = reinterpret_cast<float*>(d.out);
       if (d.flags & DF_BF16) {
         const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);

@@ -664,6 +664,7 @@ void fill_desc(const caf_gpu_system* s, const ActorRec& a, uint32_t aidx, const 
       if (g->in_dtype == CAF_BF16) d->flags |= DF_BF16;
       d->p.g.n = g->n;
       d->tcfg = gemm_tile_for(s, g->n);
+      d->p.g.unit = g->in_dtype == CAF_BF16 ? kGemmUnitBf16 : 1u;
       break;
     }
     case CAF_BHV_TANH:
