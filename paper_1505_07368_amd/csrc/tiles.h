@@ -149,6 +149,17 @@ __device__ __forceinline__ void escape_count(const T (&cr_in)[P], const T (&ci_i
 // range that the four waves share, so a claimed run of small tiles keeps
 // every wave busy while the tiles stay small enough to even out the end of
 // a batch.
+//
+// Issue priority: a SIMD issues from its oldest ready wave first, and the
+// drain's workgroups live as long as the launch, so the waves of the
+// workgroups dispatched last get only the leftover issue slots and their
+// runs take several times longer than the others'.  Runs claimed early in a
+// batch then finish last, on a nearly idle chip.  A wave therefore raises
+// its priority as its run ages (after kPrioStepTicks of the 100 MHz wall
+// clock, then twice and four times that) and drops back when the run ends,
+// so runs finish closer to the order they were claimed in.
+constexpr uint64_t kPrioStepTicks = 10000;  // 100 us
+
 template <typename T>
 __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t count, uint32_t* lds_ctr) {
   // pixels per lane: four in float (the loop dual-issues), two in double
@@ -182,7 +193,14 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t count, uint32
   if (threadIdx.x == 0) *lds_ctr = 0;
   __syncthreads();
   // A wave takes P blocks at a time, one pixel of each per lane.
+  const uint64_t run_t0 = wall_clock64();
   for (;;) {
+    {
+      const uint64_t age = wall_clock64() - run_t0;
+      if (age > 4 * kPrioStepTicks) __builtin_amdgcn_s_setprio(3);
+      else if (age > 2 * kPrioStepTicks) __builtin_amdgcn_s_setprio(2);
+      else if (age > kPrioStepTicks) __builtin_amdgcn_s_setprio(1);
+    }
     uint32_t b = 0;
     if (lane == 0) b = atomicAdd(lds_ctr, (uint32_t)P);
     b = __builtin_amdgcn_readfirstlane(b) + b0;
@@ -213,6 +231,7 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t count, uint32
       else out[at] = (uint16_t)n[k];
     }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // ---------------------------------------------------------------------------
