@@ -19,8 +19,9 @@
 //    publishes it (the drainer reserving first).  Every workgroup claims
 //    tiles of that sequence with a fetch_add on a claim cursor (see
 //    "claiming work tiles" below), and no workgroup ever waits for one that
-//    may not be resident; consecutive claimed tiles of one GEMM run as one
-//    stream of k slices.  Stateful hash-chain entries are applied by the
+//    may not be resident; consecutive claimed tiles of one GEMM (in work
+//    units of whole output tiles) run as one stream of k slices, those of one
+//    Mandelbrot message as one range of pixel blocks.  Stateful hash-chain entries are applied by the
 //    drainer itself, in mailbox order, while it holds the lock.  The
 //    workgroup finishing a message's last tile either publishes its reply
 //    (a completion record in host memory, released at system scope) or
@@ -28,10 +29,11 @@
 //    host round trip): a stage of at most kInlineStageTiles tiles runs in
 //    that workgroup at once, a larger one is published as new work tiles.
 //
-//    A launch retires as a whole once the published and drained counts
-//    have stood still for idle_ticks with an empty mailbox (batched mode:
-//    tens of microseconds, so one launch serves one burst; persistent mode:
-//    a long idle period) or at the stop flag.  Launches alternate between
+//    A launch retires as a whole once no drain pass has taken a message for
+//    idle_ticks and every published tile is claimed: a sentinel's next pass
+//    that finds the mailbox empty sets the retire flag under the drain lock
+//    (batched mode: tens of microseconds, so one launch serves one burst;
+//    persistent mode: a long idle period); or at the stop flag.  Launches alternate between
 //    two streams, so a new launch can start while the previous one finishes
 //    its last tiles; launches share all counters and cooperate.  Every
 //    device-side wait is bounded by wait_ticks of the wall clock.
@@ -338,9 +340,9 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
 
 // Tiles tile .. tile + count - 1 of one message (whole workgroup; for a GEMM
 // these are work units, each `unit` output tiles).  The tiles of a GEMM run
-// as one stream (the next tile's first slice loads while
-// the current one finishes), those of a Mandelbrot message as one range of
-// pixel blocks; other behaviours run tile by tile.
+// as one stream (the next tile's first slice loads while the current one
+// finishes), those of a Mandelbrot message as one range of pixel blocks;
+// other behaviours run tile by tile.
 template <bool kFull, int kBk = kBf16SliceK>
 __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t tile,
                                           uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
