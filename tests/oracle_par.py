@@ -17,7 +17,8 @@ import oracle
 
 
 def threads() -> int:
-    # The GPU machines give a test process 16 CPUs whatever os.cpu_count() says.
+    # At most 16 worker processes: a test host may grant fewer CPUs than
+    # os.cpu_count() reports.
     return max(1, min(16, os.cpu_count() or 1))
 
 
