@@ -134,8 +134,13 @@ typedef struct {
   int32_t grouping;      /* caf_grouping */
   uint32_t mandel_tile_px; /* pixels per Mandelbrot work tile (multiple of 256);
                               0 = 512 (plain), 1024 (batched / persistent) */
-  uint32_t gemm_tile;      /* GEMM output tile edge (64 or 128) for every n; 0 = per class */
-  uint32_t gemm_tile_class[4]; /* tile edge for n <= 64, <= 128, <= 256, > 256;
+  uint32_t gemm_tile;      /* GEMM output tile edge (64 or 128) for every n, or 256 for
+                              128 x 256 bf16 tiles; 0 = per class.  A 256 here or in
+                              a class (ring modes, full_wgs_per_cu 2) gives them to
+                              every bf16 product with n % 32 == 0 and 16-byte
+                              aligned inputs; the others get 128 or their class's
+                              edge */
+  uint32_t gemm_tile_class[4]; /* the same choice for n <= 64, <= 128, <= 256, > 256;
                                   0 = default (64 up to n = 128, else 128) */
   uint32_t full_wgs_per_cu; /* drain workgroups per compute unit while a GEMM actor
                                exists: 0 or 2 = two (64-deep bf16 slices; suits

@@ -128,7 +128,8 @@ def tune_gemm(torch, mode="batched", dtype="f32", count_per_size=256, cache_path
             A, B, code = A.to(torch.bfloat16), B.to(torch.bfloat16), cg.BF16
         esz = A.element_size()
         best_te, best_t = 0, float("inf")
-        for te in (64, 128):
+        # 256: 128 x 256 bf16 tiles (products that do not qualify get 128)
+        for te in ((64, 128, 256) if dtype == "bf16" else (64, 128)):
             s = cg.System(mode=mode, arena_bytes=2 << 30, ring_slots=max(4, count_per_size),
                           gemm_tile=te)
             try:

@@ -160,6 +160,7 @@ struct KArgs {
   uint32_t grid;
   uint32_t full;          // drain launch variant: 1 = every behaviour, 0 = all but GEMM
   uint32_t full_wgs;      // workgroups per compute unit of the full variant (2 or 3)
+  uint32_t wide;          // full launches use the variant with 128 x 256 bf16 tiles
 };
 
 // ---- work-tile geometry (host and device agree on it) -------------------
@@ -175,7 +176,9 @@ __host__ __device__ inline uint32_t mandel_blocks(uint32_t width, uint32_t rows)
 // tile order.  A unit that covers a whole product completes it without the
 // shared tile count and the release before it; units of several tiles
 // therefore suit products whose tiles are short next to that release.
+// tcfg 64 or 128: square tiles of that edge; 256: 128 x 256 tiles (bf16).
 __host__ __device__ inline uint32_t gemm_tiles(const Desc& d) {
+  if (d.tcfg == 256) return ((d.p.g.n + 127) / 128) * ((d.p.g.n + 255) / 256);
   const uint32_t t = (d.p.g.n + d.tcfg - 1) / d.tcfg;
   return t * t;
 }

@@ -299,6 +299,29 @@ __device__ __forceinline__ void hash_step(KArgsC& a, const Desc& d) {
   st_dev_rel(&act->seq_done, d.seq + 1u);
 }
 
+// LDS of a full variant: the largest work tile, two buffers of a bf16 GEMM
+// slice at TE = 128, for slices of bk (with 64-deep slices it also holds the
+// three stages of a wide bf16 tile).  The light variant only needs the drain
+// scratch.
+constexpr uint32_t smem_bytes(int bk) { return 2 * (2 * 128 * (bk + 8) * 2); }
+static_assert(smem_bytes(kBf16SliceK) >= kWideSmemBytes, "wide bf16 tiles fit the full LDS");
+
+// The square matrix tiles as calls, for the wide variant: inlined next to
+// the wide tile their registers would spill.  A call costs a register save
+// and restore per claimed run.
+__device__ __noinline__ void gemm_bf16_tile_call(const uint16_t* A, const uint16_t* B, float* C,
+                                                 uint32_t n, uint32_t te, uint32_t tile,
+                                                 uint32_t count, uint16_t* smem) {
+  if (te == 128) gemm_bf16_tile<128>(A, B, C, n, tile, count, smem);
+  else gemm_bf16_tile<64>(A, B, C, n, tile, count, smem);
+}
+__device__ __noinline__ void gemm_f32_tile_call(const float* A, const float* B, float* C,
+                                                uint32_t n, uint32_t te, uint32_t tile,
+                                                uint32_t count, float* smem) {
+  if (te == 128) gemm_f32_tile<128>(A, B, C, n, tile, count, smem);
+  else gemm_f32_tile<64>(A, B, C, n, tile, count, smem);
+}
+
 // kFull = false compiles every behaviour except GEMM: without the matrix
 // tiles the kernel needs far fewer registers and runs more waves per SIMD.
 // One tile of every behaviour except GEMM (see run_tiles).
@@ -343,11 +366,34 @@ __device__ __forceinline__ void run_tile(KArgsC& a, const Desc& d, uint32_t tile
 // as one stream (the next tile's first slice loads while the current one
 // finishes), those of a Mandelbrot message as one range of pixel blocks;
 // other behaviours run tile by tile.
-template <bool kFull, int kBk = kBf16SliceK>
+template <bool kFull, int kBk = kBf16SliceK, bool kWide = false>
 __device__ __forceinline__ void run_tiles(KArgsC& a, const Desc& d, uint32_t tile,
                                           uint32_t count, uint8_t* smem, uint32_t* lds_ctr) {
-  if constexpr (kFull) {
+  if constexpr (kWide) {
     if (d.behavior == CAF_BHV_GEMM) {
+      // work units -> output tiles
+      const uint32_t u = gemm_unit(d), all = gemm_tiles(d);
+      const uint32_t t0 = tile * u;
+      const uint32_t cnt = min(t0 + count * u, all) - t0;
+      float* C = reinterpret_cast<float*>(d.out);
+      if (d.flags & DF_BF16) {
+        const uint16_t* A = reinterpret_cast<const uint16_t*>(d.in0);
+        const uint16_t* B = reinterpret_cast<const uint16_t*>(d.in1);
+        if (d.tcfg == 256) gemm_bf16_tile_wide(A, B, C, d.p.g.n, t0, cnt, (uint16_t*)smem);
+        else gemm_bf16_tile_call(A, B, C, d.p.g.n, d.tcfg, t0, cnt, (uint16_t*)smem);
+      } else {
+        gemm_f32_tile_call(reinterpret_cast<const float*>(d.in0),
+                           reinterpret_cast<const float*>(d.in1), C, d.p.g.n, d.tcfg, t0, cnt,
+                           (float*)smem);
+      }
+      return;
+    }
+  } else if constexpr (kFull) {
+    if (d.behavior == CAF_BHV_GEMM) {
+      if (d.tcfg == 256) {  // wide tiles run in the wide variant only
+        if (threadIdx.x == 0) st_dev(&a.sstate[d.slot].status, (int32_t)CAF_E_DEVICE);
+        return;
+      }
       // work units -> output tiles
       const uint32_t u = gemm_unit(d), all = gemm_tiles(d);
       const uint32_t t0 = tile * u;
@@ -417,10 +463,6 @@ __device__ __forceinline__ void run_inline_stages(KArgsC& a, uint32_t slot, uint
   }
 }
 
-// LDS of a full variant: the largest work tile, two buffers of a bf16 GEMM
-// slice at TE = 128, for slices of bk.  The light variant only needs the
-// drain scratch.
-constexpr uint32_t smem_bytes(int bk) { return 2 * (2 * 128 * (bk + 8) * 2); }
 constexpr uint32_t kSmemBytes = smem_bytes(kBf16SliceK);
 
 // ---- one launch per message -------------------------------------------------
@@ -966,7 +1008,7 @@ __device__ void fill_reservations_locked(KArgsC& a) {
 enum : uint32_t { CMD_IDLE = 0, CMD_TILE = 1, CMD_DRAIN = 2 };
 constexpr uint32_t kSentinels = 16;
 
-template <bool kFull, int kBk = kBf16SliceK>
+template <bool kFull, int kBk = kBf16SliceK, bool kWide = false>
 __device__ __forceinline__ void drain_body(KArgsC& a) {
   __shared__ __align__(16) uint8_t smem[kFull ? smem_bytes(kBk) : kSmemLight];
   __shared__ __align__(16) DevSlot s_slot;
@@ -1085,7 +1127,7 @@ __device__ __forceinline__ void drain_body(KArgsC& a) {
         // A failed tile stops the message's other tiles; a one-tile message
         // cannot have failed before its tile runs.
         if (ntiles == 1 || s_status == CAF_OK)
-          run_tiles<kFull, kBk>(a, d, tile, run, smem, &s_ctr);
+          run_tiles<kFull, kBk, kWide>(a, d, tile, run, smem, &s_ctr);
         __syncthreads();
         if (t == 0) s_cont = finish_tiles(a, d, ntiles, run, true) ? 1u : 0u;
         __syncthreads();
@@ -1189,6 +1231,13 @@ drain_kernel_full3(KArgs) {
   drain_body<true, 32>(kargs());
 }
 
+// The full variant for systems that use 128 x 256 bf16 tiles (two
+// workgroups per compute unit); its square matrix tiles are calls.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+drain_kernel_wide(KArgs) {
+  drain_body<true, kBf16SliceK, true>(kargs());
+}
+
 // The light variant asks for five waves per SIMD (at most 96 registers).
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
 drain_kernel_light(KArgs) {
@@ -1211,14 +1260,19 @@ const void* plain_kernel_fn(bool full) {
 }
 
 hipError_t launch_drain(const KArgs& a, hipStream_t s) {
-  if (a.full && a.full_wgs == 3)
+  if (a.full && a.wide)
+    hipLaunchKernelGGL(drain_kernel_wide, dim3(a.grid), dim3(kThreads), 0, s, a);
+  else if (a.full && a.full_wgs == 3)
     hipLaunchKernelGGL(drain_kernel_full3, dim3(a.grid), dim3(kThreads), 0, s, a);
   else if (a.full) hipLaunchKernelGGL(drain_kernel_full, dim3(a.grid), dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL(drain_kernel_light, dim3(a.grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t drain_occupancy(bool full, uint32_t full_wgs, int* blocks_per_cu) {
+hipError_t drain_occupancy(bool full, uint32_t full_wgs, bool wide, int* blocks_per_cu) {
+  if (full && wide)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel_wide,
+                                                        kThreads, 0);
   if (full && full_wgs == 3)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, drain_kernel_full3,
                                                         kThreads, 0);

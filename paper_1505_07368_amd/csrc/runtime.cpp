@@ -42,7 +42,7 @@
 namespace cafgpu {
 hipError_t launch_plain(const KArgs& a, const Desc& d, uint32_t ntiles, hipStream_t s);
 hipError_t launch_drain(const KArgs& a, hipStream_t s);
-hipError_t drain_occupancy(bool full, uint32_t full_wgs, int* blocks_per_cu);
+hipError_t drain_occupancy(bool full, uint32_t full_wgs, bool wide, int* blocks_per_cu);
 const void* plain_kernel_fn(bool full);
 }  // namespace cafgpu
 
@@ -616,12 +616,27 @@ int check_signature(const ActorRec& a, const void* args, uint64_t args_bytes, co
   return CAF_E_INVALID;
 }
 
-uint32_t gemm_tile_for(const caf_gpu_system* s, uint32_t n) {
-  if (s->gemm_tile == 64 || s->gemm_tile == 128) return s->gemm_tile;
-  const uint32_t cls = n <= 64 ? 0u : n <= 128 ? 1u : n <= 256 ? 2u : 3u;
-  const uint32_t t = s->cfg.gemm_tile_class[cls];
-  if (t == 64 || t == 128) return t;
-  return n <= 128 ? 64u : 128u;
+// Tile choice of a product (tcfg).  A system that runs the wide drain
+// variant gives 256 (128 x 256 bf16 tiles) to every product that qualifies
+// -- bf16 inputs, n % 32 == 0, 16-byte aligned device inputs (host inputs
+// are staged into the arena, which is) -- whatever its size class asks for:
+// in that variant the square tiles are calls.  Other products get their
+// class's edge, 128 where that is 256.
+uint32_t gemm_tile_for(const caf_gpu_system* s, const caf_gemm_args* g, const caf_buf* in) {
+  const uint32_t n = g->n;
+  if (s->kargs.wide && g->in_dtype == CAF_BF16 && n % 32 == 0) {
+    bool aligned = true;
+    for (int i = 0; i < 2; ++i)
+      if (in[i].on_device && ((uintptr_t)in[i].data & 15u) != 0) aligned = false;
+    if (aligned) return 256;
+  }
+  uint32_t t = s->gemm_tile;
+  if (t == 0) {
+    const uint32_t cls = n <= 64 ? 0u : n <= 128 ? 1u : n <= 256 ? 2u : 3u;
+    t = s->cfg.gemm_tile_class[cls];
+    if (t == 0) t = n <= 128 ? 64u : 128u;
+  }
+  return t == 256 ? 128u : t;
 }
 
 // Builds the descriptor of the first stage (all fields except slot, seq and
@@ -663,7 +678,7 @@ void fill_desc(const caf_gpu_system* s, const ActorRec& a, uint32_t aidx, const 
       const caf_gemm_args* g = (const caf_gemm_args*)args;
       if (g->in_dtype == CAF_BF16) d->flags |= DF_BF16;
       d->p.g.n = g->n;
-      d->tcfg = gemm_tile_for(s, g->n);
+      d->tcfg = gemm_tile_for(s, g, in);
       d->p.g.unit = g->in_dtype == CAF_BF16 ? kGemmUnitBf16 : 1u;
       break;
     }
@@ -1043,9 +1058,10 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
                                                   ? 512u
                                                   : 1024u);
   if (mpx % 256 != 0 || mpx > 65536) return CAF_E_INVALID;
-  if (cfg->gemm_tile != 0 && cfg->gemm_tile != 64 && cfg->gemm_tile != 128) return CAF_E_INVALID;
+  auto tile_ok = [](uint32_t t) { return t == 0 || t == 64 || t == 128 || t == 256; };
+  if (!tile_ok(cfg->gemm_tile)) return CAF_E_INVALID;
   for (uint32_t t : cfg->gemm_tile_class)
-    if (t != 0 && t != 64 && t != 128) return CAF_E_INVALID;
+    if (!tile_ok(t)) return CAF_E_INVALID;
   if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT) return CAF_E_INVALID;
   if (cfg->full_wgs_per_cu != 0 && cfg->full_wgs_per_cu != 2 && cfg->full_wgs_per_cu != 3)
     return CAF_E_INVALID;
@@ -1059,6 +1075,15 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   s->mandel_tile_px = mpx;
   s->gemm_tile = cfg->gemm_tile;
   s->kargs.full_wgs = cfg->full_wgs_per_cu == 3 ? 3u : 2u;
+  {
+    // 128 x 256 bf16 tiles: asked for by a tile choice of 256, in a ring
+    // mode with two full workgroups per CU (their LDS holds the tile's
+    // three stages); full launches then use the wide variant.
+    bool asked = cfg->gemm_tile == 256;
+    for (uint32_t t : cfg->gemm_tile_class) asked = asked || t == 256;
+    const bool ring = cfg->mode != CAF_MODE_PLAIN && cfg->mode != CAF_MODE_PLAIN_GRAPH;
+    s->kargs.wide = asked && ring && s->kargs.full_wgs == 2 ? 1u : 0u;
+  }
   s->arena.init((uint64_t)(uintptr_t)cfg->arena, cfg->arena_bytes);
   bool ok = true;
   auto chk = [&](hipError_t e) {
@@ -1113,8 +1138,8 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   // Default grid: every workgroup resident (the kernel never needs that,
   // but it is the most work in flight).
   int occ_full = 1, occ_light = 1;
-  if (ok) chk(drain_occupancy(true, s->kargs.full_wgs, &occ_full));
-  if (ok) chk(drain_occupancy(false, s->kargs.full_wgs, &occ_light));
+  if (ok) chk(drain_occupancy(true, s->kargs.full_wgs, s->kargs.wide != 0, &occ_full));
+  if (ok) chk(drain_occupancy(false, s->kargs.full_wgs, false, &occ_light));
   if (occ_full < 1) occ_full = 1;
   if (occ_light < 1) occ_light = 1;
   s->grid_full = cfg->grid ? cfg->grid : (uint32_t)(cus * occ_full);

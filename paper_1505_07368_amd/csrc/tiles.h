@@ -639,6 +639,198 @@ __device__ __forceinline__ void gemm_bf16_tile(const uint16_t* __restrict__ A, c
   }
 }
 
+// Wide bf16 tiles: 128 x 256 blocks of C (each wave 64 x 128, 2 x 4 MFMA
+// blocks), for products with n % 32 == 0 and 16-byte aligned operands.  A
+// wider block reads a quarter fewer operand bytes per flop than two 128 x 128
+// tiles; a batch of mixed products is bound by those reads from beyond L2
+// (each tile re-reads the A and B panels it shares with its neighbours).
+// They run in a drain variant of their own, whose other matrix tiles are
+// out of line: inlined next to these, their registers would spill.
+//
+// Operands go from global memory straight into a three-stage LDS ring
+// (global_load_lds_dwordx4: 16 bytes per lane, laid out lane by lane per wave
+// instruction), 32-deep k slices of 24 KB, so two slices are in flight while
+// the third is multiplied and no registers stage them.  Rows are XOR-swizzled
+// in 16-byte chunks: A (row-major, 64-byte rows) by (row / 2) % 4, B
+// (row-major k x n, 512-byte rows) by 2 * (k % 4), so the fragment reads of
+// a wave spread over the LDS banks.  A fragments (8 consecutive k of one
+// row) are 16-byte LDS reads; B fragments (8 consecutive k of one column)
+// come from the transposing read ds_read_b64_tr_b16: across 16 lanes that
+// each address four consecutive bf16 of a row, lane j receives element j % 4
+// of the rows addressed by lanes j / 4, j / 4 + 4, j / 4 + 8 and j / 4 + 12
+// -- so lanes addressing B[k + r / 4][n0 + 4 (r % 4)] (r = 0..15) hand lane j
+// the column B[k .. k + 3][n0 + j].  Two such reads give a lane its 8 k.
+//
+// The direct loads are waited for explicitly (vmcnt), then a barrier without
+// a memory fence makes every wave's data visible.  The fragment reads are
+// issued from inline assembly that waits for them itself (lgkmcnt): issued
+// as builtins, the compiler would wait for every direct load in flight
+// before them, as it cannot tell that they read another stage.  Output
+// stores share the vmcnt counter with the loads, so after a tile's stores
+// the next slice is waited for with vmcnt(0).
+//
+// Tile t of a product covers row block t / ceil(n / 256) and column block
+// t % ceil(n / 256).  smem: 72 KB.
+constexpr uint32_t kWideStages = 3;
+constexpr uint32_t kWideSmemBytes = kWideStages * (128 * 32 + 32 * 256) * 2;
+
+// s_waitcnt limiting only vmcnt (expcnt 7 and lgkmcnt 15 impose no wait)
+#define CAF_WAIT_VMCNT(N) \
+  __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+
+// Workgroup barrier without the memory fence of __syncthreads, fenced
+// against compiler reordering of the LDS accesses around it.
+__device__ __forceinline__ void barrier_no_fence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void gemm_bf16_tile_wide(const uint16_t* __restrict__ A,
+                                                    const uint16_t* __restrict__ B,
+                                                    float* __restrict__ C, uint32_t n,
+                                                    uint32_t tile0, uint32_t count, uint16_t* smem) {
+  constexpr uint32_t TM = 128, TN = 256, BK = 32, WM = 2, WN = 4, NS = kWideStages;
+  constexpr uint32_t A_BYTES = TM * BK * 2, B_BYTES = BK * TN * 2, STAGE = A_BYTES + B_BYTES;
+  constexpr uint32_t LOADS = (A_BYTES + B_BYTES) / 16 / kThreads;  // direct loads per thread and slice
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(3))) uint8_t lds_u8;
+  const auto Ag = global_ptr(A);
+  const auto Bg = global_ptr(B);
+  const auto Cg = global_ptr(C);
+  const uint32_t t = threadIdx.x, lane = lane_id(), w = wave_id();
+  const uint32_t wm = w >> 1, wn = w & 1;
+  lds_u8* lds = (lds_u8*)smem;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)lds;
+  floatx16 acc[WM][WN];
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (uint32_t i = 0; i < WM; ++i)
+#pragma unroll
+      for (uint32_t j = 0; j < WN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  };
+  zero_acc();
+  const uint32_t nk = n / BK, tpr = (n + TN - 1) / TN;
+  const uint32_t steps = count * nk;
+  auto coords = [&](uint32_t tl, uint32_t& tm, uint32_t& tn) {
+    tm = tl / tpr;
+    tn = tl - tm * tpr;
+  };
+  // Direct loads of slice s into stage s % NS.  Rows beyond n read the last
+  // row and columns beyond n the first ones: they only feed rows and
+  // columns of C that are not stored.
+  auto issue = [&](uint32_t s) {
+    const uint32_t k0 = (s % nk) * BK;
+    uint32_t tm, tn;
+    coords(tile0 + s / nk, tm, tn);
+    lds_u8* st = lds + (s % NS) * STAGE;
+#pragma unroll
+    for (uint32_t q = 0; q < A_BYTES / 16 / kThreads; ++q) {
+      const uint32_t idx = q * kThreads + t;  // 16-byte chunk of the stage's A
+      const uint32_t row = idx >> 2, c = (idx & 3) ^ ((row >> 1) & 3);
+      const uint32_t grow = min(tm * TM + row, n - 1u);
+      __builtin_amdgcn_global_load_lds(
+          (const CAF_GLOBAL void*)(Ag + (uint64_t)grow * n + k0 + c * 8),
+          (__attribute__((address_space(3))) void*)(st + (q * kThreads + w * 64) * 16), 16, 0, 0);
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < B_BYTES / 16 / kThreads; ++q) {
+      const uint32_t idx = q * kThreads + t;  // 16-byte chunk of the stage's B
+      const uint32_t krow = idx >> 5, c = (idx & 31) ^ ((krow & 3) << 1);
+      uint32_t gcol = tn * TN + c * 8;
+      if (gcol >= n) gcol = 0;
+      __builtin_amdgcn_global_load_lds(
+          (const CAF_GLOBAL void*)(Bg + (uint64_t)(k0 + krow) * n + gcol),
+          (__attribute__((address_space(3))) void*)(st + A_BYTES + (q * kThreads + w * 64) * 16), 16,
+          0, 0);
+    }
+  };
+  auto compute = [&](uint32_t s) {
+    const uint32_t st = lds0 + (s % NS) * STAGE, sb = st + A_BYTES;
+    const uint32_t g = lane >> 4, j = lane & 15;
+#pragma unroll
+    for (uint32_t ks = 0; ks < BK; ks += 16) {
+      uint32_t aad[WM], bad[WN][2];
+#pragma unroll
+      for (uint32_t i = 0; i < WM; ++i) {
+        const uint32_t row = wm * 64 + i * 32 + (lane & 31);
+        const uint32_t kc = (ks >> 3) + (lane >> 5);
+        aad[i] = st + row * (BK * 2) + (kc ^ ((row >> 1) & 3)) * 16;
+      }
+#pragma unroll
+      for (uint32_t jb = 0; jb < WN; ++jb) {
+        const uint32_t n0 = wn * 128 + jb * 32 + (g & 1) * 16;
+        const uint32_t kq = ks + (g >> 1) * 8;
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+          const uint32_t krow = kq + h * 4 + (j >> 2);
+          const uint32_t e = n0 + 4 * (j & 3);  // first column this lane addresses
+          bad[jb][h] = sb + krow * (TN * 2) + ((e >> 3) ^ ((krow & 3) << 1)) * 16 + (e & 7) * 2;
+        }
+      }
+      u32x4 a0, a1;
+      u32x2 b[WN][2];
+      asm volatile(
+          "ds_read_b128 %0, %10\n\t"
+          "ds_read_b128 %1, %11\n\t"
+          "ds_read_b64_tr_b16 %2, %12\n\t"
+          "ds_read_b64_tr_b16 %3, %13\n\t"
+          "ds_read_b64_tr_b16 %4, %14\n\t"
+          "ds_read_b64_tr_b16 %5, %15\n\t"
+          "ds_read_b64_tr_b16 %6, %16\n\t"
+          "ds_read_b64_tr_b16 %7, %17\n\t"
+          "ds_read_b64_tr_b16 %8, %18\n\t"
+          "ds_read_b64_tr_b16 %9, %19\n\t"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(a0), "=&v"(a1), "=&v"(b[0][0]), "=&v"(b[0][1]), "=&v"(b[1][0]), "=&v"(b[1][1]),
+            "=&v"(b[2][0]), "=&v"(b[2][1]), "=&v"(b[3][0]), "=&v"(b[3][1])
+          : "v"(aad[0]), "v"(aad[1]), "v"(bad[0][0]), "v"(bad[0][1]), "v"(bad[1][0]),
+            "v"(bad[1][1]), "v"(bad[2][0]), "v"(bad[2][1]), "v"(bad[3][0]), "v"(bad[3][1]));
+      bf16x8 af[WM], bf[WN];
+      af[0] = __builtin_bit_cast(bf16x8, a0);
+      af[1] = __builtin_bit_cast(bf16x8, a1);
+#pragma unroll
+      for (uint32_t jb = 0; jb < WN; ++jb) {
+        struct {
+          u32x2 lo, hi;
+        } pr = {b[jb][0], b[jb][1]};
+        bf[jb] = __builtin_bit_cast(bf16x8, pr);
+      }
+#pragma unroll
+      for (uint32_t i = 0; i < WM; ++i)
+#pragma unroll
+        for (uint32_t jb = 0; jb < WN; ++jb)
+          acc[i][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[jb], acc[i][jb], 0, 0, 0);
+    }
+  };
+  for (uint32_t s = 0; s < NS - 1 && s < steps; ++s) issue(s);
+  bool stores_pending = false;
+  for (uint32_t s = 0; s < steps; ++s) {
+    // this thread's loads of slice s: the slice issued after it (if any) may
+    // stay in flight, unless output stores were issued since
+    if (stores_pending || s + 1 == steps) CAF_WAIT_VMCNT(0);
+    else CAF_WAIT_VMCNT(LOADS);
+    stores_pending = false;
+    barrier_no_fence();  // every wave's slice s is in LDS, slice s - 1 is read
+    if (s + NS - 1 < steps) issue(s + NS - 1);
+    compute(s);
+    if (s % nk == nk - 1) {
+      uint32_t tm, tn;
+      coords(tile0 + s / nk, tm, tn);
+#pragma unroll
+      for (uint32_t i = 0; i < WM; ++i)
+#pragma unroll
+        for (uint32_t jb = 0; jb < WN; ++jb)
+          store_c<128>(Cg, n, tm * TM + wm * 64 + i * 32, tn * TN + wn * 128 + jb * 32, acc[i][jb]);
+      zero_acc();
+      stores_pending = true;
+    }
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // Support behaviours (pipeline stages and ping-pong).
 // ---------------------------------------------------------------------------

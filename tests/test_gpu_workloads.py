@@ -129,12 +129,15 @@ def _gemm_batch(cg, torch, s, sizes, dtype):
 
 @pytest.mark.parametrize("wgs", [2, 3])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("te", [64, 128])
+@pytest.mark.parametrize("te", [64, 128, 256])
 def test_gemm_batch_sampled(dtype, te, wgs):
-    """A drained batch of mixed sizes with every tile edge and both full
+    """A drained batch of mixed sizes with every tile choice and both full
     drain variants (2 workgroups per CU with 64-deep bf16 slices, 3 with
-    32-deep ones); one message of each size (n = 512 included) checked
-    against the FP64 oracle, every output checked finite."""
+    32-deep ones; 256 = 128 x 256 bf16 tiles in the wide variant, whose
+    square tiles are calls -- fp32 products run there as 128 x 128, and the
+    3-workgroup variant replaces 256 by 128); one message of each size
+    (n = 512 included) checked against the FP64 oracle, every output
+    checked finite."""
     import torch
     from paper_1505_07368_amd import binding as cg
     sizes = gen.gemm_sizes(0, 48)
@@ -223,7 +226,7 @@ def test_serving_mix_full(wgs):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_gemm_bench_batch_full_size(dtype):
+def test_gemm_bench_batch_full_size(dtype, tile_class=(0, 0, 0, 0)):
     """The benchmark's GEMM leg as timed: 4096 requests, n ~ U{64..512},
     inputs drawn on the device, batched drain with max_batch 1024.  Every
     output is checked finite; every 64th product (and one of each size)
@@ -244,7 +247,8 @@ def test_gemm_bench_batch_full_size(dtype):
         A, B, code = A.to(torch.bfloat16), B.to(torch.bfloat16), cg.BF16
     C = torch.full((total,), float("nan"), device="cuda")
     esz = A.element_size()
-    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=count, max_batch=1024)
+    s = cg.System(mode="batched", arena_bytes=1 << 30, ring_slots=count, max_batch=1024,
+                  gemm_tile_class=tile_class)
     try:
         a = s.spawn(cg.BHV_GEMM)
         args = np.zeros(count, cg.NP_GEMM)
@@ -438,6 +442,50 @@ def test_gemm_large_single_message(dtype):
         s.shutdown()
     err = rel_fro(c, oracle.gemm(A, B, dtype))
     assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gemm_bench_batch_full_size_wide(dtype):
+    """The benchmark's batch in a system that asks for 128 x 256 tiles from
+    n = 256 on (the wide variant: every bf16 product gets them, fp32
+    products run the square tiles as calls), checked as above."""
+    test_gemm_bench_batch_full_size(dtype, tile_class=(128, 128, 256, 256))
+
+
+@pytest.mark.parametrize("mode", ["batched", "persistent"])
+def test_gemm_bf16_wide_tiles(mode):
+    """128 x 256 bf16 tiles (direct-to-LDS ring, transposing B reads) for
+    every n % 32 == 0 from 32 to 544, ragged against both tile dimensions;
+    n % 32 != 0 and an input 8 bytes off 16-byte alignment fall back to
+    128 x 128 tiles.  Every product compared in full with the FP64 oracle."""
+    import torch
+    from paper_1505_07368_amd import binding as cg
+    sizes = [32, 64, 96, 128, 160, 224, 256, 288, 384, 512, 544, 100, 200, 520]
+    with cg.System(mode=mode, arena_bytes=1 << 30, ring_slots=64, gemm_tile=256) as s:
+        a = s.spawn(cg.BHV_GEMM)
+        cases = []
+        for i, n in enumerate(sizes):
+            A, B = gen.gemm_pair(1500 + i, n, "bf16")
+            tA = torch.from_numpy(A.view(np.int16)).cuda().view(torch.bfloat16)
+            tB = torch.from_numpy(B.view(np.int16)).cuda().view(torch.bfloat16)
+            cases.append((n, A, B, tA, tB))
+        # an operand 8 bytes past a 16-byte boundary
+        n = 256
+        A, B = gen.gemm_pair(1600, n, "bf16")
+        pad = torch.zeros(n * n + 4, dtype=torch.int16, device="cuda")
+        pad[4:] = torch.from_numpy(A.view(np.int16).ravel()).cuda()
+        tA = pad[4:].view(torch.bfloat16)
+        assert tA.data_ptr() % 16 == 8
+        tB = torch.from_numpy(B.view(np.int16)).cuda().view(torch.bfloat16)
+        cases.append((n, A, B, tA, tB))
+        torch.cuda.synchronize()
+        futs = [s.request(a, cg.caf_gemm_args(n, cg.BF16), inputs=[tA, tB])
+                for n, _, _, tA, tB in cases]
+        for (n, A, B, _, _), f in zip(cases, futs):
+            st, C = f.result()
+            assert st == cg.OK, (n, st)
+            err = rel_fro(C.cpu().numpy().reshape(n, n), oracle.gemm(A, B, "bf16"))
+            assert err <= 1e-5, (n, err)
 
 
 @pytest.mark.parametrize("wgs", [2, 3])
