@@ -559,6 +559,9 @@ def main():
                     help="comma list of the legs to run beside the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--gemm-dtypes", default="f32,bf16", help="GEMM leg input types")
+    ap.add_argument("--gemm-tile-class", default="",
+                    help="GEMM leg tile choice per size class (e.g. 64,128,256,256) instead "
+                    "of the autotuned one")
     ap.add_argument("--headline-fp", default="f32", choices=("f32", "f64"),
                     help="precision of the headline leg (f64: for profiling the double "
                     "path; the reported metric is defined in f32)")
@@ -713,12 +716,16 @@ def main():
 
     def leg_gemm(dt):
         tc = (0, 0, 0, 0)
-        if not args.no_tune:
+        if args.gemm_tile_class:
+            tc = tuple(int(x) for x in args.gemm_tile_class.split(","))
+            assert len(tc) == 4, "--gemm-tile-class takes four edges"
+        elif not args.no_tune:
             log(f"[bench] autotune gemm {dt}")
             tc = autotune.tune_gemm(torch, dtype=dt, cache_path=cache)
             tuned[f"gemm_{dt}_tile_class"] = tc
         log(f"[bench] gemm batch {dt}")
         result[f"gemm_{dt}"] = gemm_leg(cg, torch, dt, tile_class=tc)
+        result[f"gemm_{dt}"]["tile_class"] = list(tc)
 
     def leg_pipeline():
         log("[bench] pipeline")
