@@ -165,10 +165,18 @@ struct KArgs {
 
 // ---- work-tile geometry (host and device agree on it) -------------------
 
-__host__ __device__ inline uint32_t mandel_blocks(uint32_t width, uint32_t rows) {
-  uint32_t bw = (width + kMandelBlockW - 1) / kMandelBlockW;
-  uint32_t bh = (rows + kMandelBlockH - 1) / kMandelBlockH;
-  return bw * bh;
+// A wave iterates a group of blocks at once, one pixel of each per lane:
+// 2 block rows x 2 block columns (8 x 32 pixels) in float, 2 x 1 (8 x 16) in
+// double.  Blocks are numbered group by group, groups row-major; the count
+// includes the blocks of the partial groups at the right and bottom edges.
+constexpr uint32_t kMandelGroupRows = 2;
+__host__ __device__ constexpr uint32_t mandel_group_cols(bool fp64) { return fp64 ? 1u : 2u; }
+__host__ __device__ inline uint32_t mandel_blocks(uint32_t width, uint32_t rows, bool fp64) {
+  const uint32_t gc = mandel_group_cols(fp64);
+  const uint32_t bw = (width + kMandelBlockW - 1) / kMandelBlockW;
+  const uint32_t bh = (rows + kMandelBlockH - 1) / kMandelBlockH;
+  return ((bw + gc - 1) / gc) * ((bh + kMandelGroupRows - 1) / kMandelGroupRows) * gc *
+         kMandelGroupRows;
 }
 
 // A product's output tiles (tcfg x tcfg blocks of C) and the work units
@@ -195,7 +203,7 @@ __host__ __device__ inline uint32_t desc_ntiles(const Desc& d) {
     case CAF_BHV_MANDELBROT: {
       uint32_t w = d.p.m64.width, r = d.p.m64.rows;  // same offsets in m32
       uint32_t bpt = d.tcfg / 64;
-      uint32_t nb = mandel_blocks(w, r);
+      uint32_t nb = mandel_blocks(w, r, (d.flags & DF_FP64) != 0);
       return nb == 0 ? 1u : (nb + bpt - 1) / bpt;  // an empty tile still replies
     }
     case CAF_BHV_GEMM: {

@@ -47,11 +47,14 @@ __device__ inline uint32_t wave_id() { return threadIdx.x >> 6; }
 //
 // A message covers global rows [row0, row0 + rows) of a width-wide image and
 // replies uint16 counts, row-major [rows][width].  Its pixels are cut into
-// 4 x 16 blocks, one block per wave64 at a time (lane -> row lane/16,
-// column lane%16: each row segment is a contiguous 32-byte store), and a
-// work tile is tcfg/64 consecutive blocks.  The waves of the workgroup take
-// blocks of the tile from an LDS counter, so a slow block does not hold the
-// others.  Inside a block every lane iterates its own pixel; the wave
+// 4 x 16 blocks (lane -> row lane/16, column lane%16: each row segment is a
+// contiguous 32-byte store), numbered in groups of P blocks -- 8 x 32 pixels
+// in float, 8 x 16 in double -- that a wave iterates together, and a work
+// tile is tcfg/64 consecutive blocks.  A compact group holds pixels of
+// similar escape times, so fewer of a wave's lanes idle while its slowest
+// pixel finishes than in a 4 x 64 row of blocks.  The waves of the
+// workgroup take groups of the tile from an LDS counter, so a slow group
+// does not hold the others.  Every lane iterates its own pixels; the wave
 // leaves the loop as soon as the ballot of lanes that have not escaped is
 // empty -- the early exit is wave-uniform and no lane's count moves past
 // its escape.
@@ -184,15 +187,19 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t count, uint32
   const auto pal = global_ptr(reinterpret_cast<const uint32_t*>(d.in0));
   const uint32_t pal_last = d.numel - 1u;
   const auto out32 = global_ptr(reinterpret_cast<uint32_t*>(d.out));
+  constexpr uint32_t GC = sizeof(T) == 8 ? 1u : 2u;  // a group's block columns
+  static_assert(GC == mandel_group_cols(sizeof(T) == 8) && GC * kMandelGroupRows == P,
+                "a wave's group is P blocks");
   const uint32_t bw = (width + kMandelBlockW - 1) / kMandelBlockW;
-  const uint32_t nb = mandel_blocks(width, rows);
+  const uint32_t gw = (bw + GC - 1) / GC;  // groups across
+  const uint32_t nb = mandel_blocks(width, rows, sizeof(T) == 8);
   const uint32_t bpt = d.tcfg / 64;
   const uint32_t b0 = tile * bpt;
   const uint32_t b1 = min(nb, b0 + bpt * count);
   const uint32_t lane = lane_id();
   if (threadIdx.x == 0) *lds_ctr = 0;
   __syncthreads();
-  // A wave takes P blocks at a time, one pixel of each per lane.
+  // A wave takes a group of P blocks at a time, one pixel of each per lane.
   const uint64_t run_t0 = wall_clock64();
   for (;;) {
     {
@@ -211,7 +218,9 @@ __device__ void mandel_tile(const Desc& d, uint32_t tile, uint32_t count, uint32
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const uint32_t bk = b + k;
-      const uint32_t by = bk / bw, bx = bk - by * bw;
+      const uint32_t q = bk / P, r = bk % P;  // group, block within it
+      const uint32_t qy = q / gw, qx = q - qy * gw;
+      const uint32_t by = qy * kMandelGroupRows + r / GC, bx = qx * GC + r % GC;
       y[k] = by * kMandelBlockH + lane / kMandelBlockW;
       x[k] = bx * kMandelBlockW + lane % kMandelBlockW;
       v[k] = bk < b1 && y[k] < rows && x[k] < width;
