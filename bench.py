@@ -43,8 +43,55 @@ OPS_PER_ITER = 9
 HBM_PEAK = 8.0e12
 
 
+# time of the last progress line (the leg watchdog's clock)
+_PROGRESS = [time.monotonic()]
+# a leg that prints no progress line for this long is taken to be stuck
+LEG_STALL_S = 150.0
+
+
 def log(*a):
+    _PROGRESS[0] = time.monotonic()
     print(*a, file=sys.stderr, flush=True)
+
+
+def start_leg_watchdog(result, tuned, current):
+    """Ends the run if a leg beside the headline stops making progress: the
+    leg is recorded as timed out, the legs after it as not run, and the one
+    JSON line (headline included) is printed before the process exits.  A
+    leg stuck in a library call cannot be interrupted from Python, and the
+    process's exit ends its GPU work."""
+    import threading
+
+    def watch():
+        while True:
+            time.sleep(1.0)
+            leg = current[0]
+            if leg is None or time.monotonic() - _PROGRESS[0] < LEG_STALL_S:
+                continue
+            log(f"[bench] leg {leg}: no progress for {LEG_STALL_S:g} s; ending the run")
+            out = None
+            for _ in range(10):  # the stuck thread is inside a library call
+                try:
+                    out = json.loads(json.dumps(result))
+                    break
+                except RuntimeError:
+                    time.sleep(0.1)
+            if out is None:
+                out = {k: result[k] for k in ("metric", "value", "unit")}
+            msg = (f"no progress for {LEG_STALL_S:g} s; this leg and the legs after it did "
+                   "not finish")
+            if isinstance(out.get(leg), dict):
+                out[leg]["error"] = msg  # keep what the leg measured before it stalled
+            else:
+                out[leg] = {"error": msg}
+            try:
+                out["tuned"] = json.loads(json.dumps(tuned))
+            except (RuntimeError, TypeError, ValueError):
+                pass
+            print(json.dumps(out), flush=True)
+            os._exit(0)
+
+    threading.Thread(target=watch, daemon=True).start()
 
 
 # rocprofv3 summary of the headline's dominant kernel (durations and counters).
@@ -656,16 +703,24 @@ def main():
                     result["roofline"]["achieved"] * 1e12 / ops_s, 4)
     legs = set() if args.quick else set(args.legs.split(","))
 
+    current = [None]
+    start_leg_watchdog(result, tuned, current)
+
     def run_leg(name, fn):
         """Runs one leg beside the headline; a failure is recorded in its
         place (with the traceback on stderr) so the headline line still
-        prints."""
+        prints, and a leg that stops making progress ends the run with the
+        results so far (start_leg_watchdog)."""
+        current[0] = name
+        _PROGRESS[0] = time.monotonic()
         try:
             fn()
         except Exception as e:  # noqa: BLE001 -- any leg failure is reported, not fatal
             import traceback
             traceback.print_exc()
             result[name] = {"error": f"{type(e).__name__}: {e}"}
+        finally:
+            current[0] = None
 
     def leg_fp64():
         log("[bench] batched fp64")
