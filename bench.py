@@ -820,13 +820,15 @@ def main():
     if "gemm" in legs:
         for dt in args.gemm_dtypes.split(","):
             run_leg(f"gemm_{dt}", lambda dt=dt: leg_gemm(dt))
-    for name, fn in (("pipeline", leg_pipeline), ("serving", leg_serving),
-                     ("offload", leg_offload)):
+    # the CPU baseline and the offload leg before serving, the longest and
+    # most loaded leg: if a leg stalls, the watchdog's line still has them
+    if not args.no_cpu:
+        run_leg("cpu_baseline", leg_cpu)
+    for name, fn in (("pipeline", leg_pipeline), ("offload", leg_offload),
+                     ("serving", leg_serving)):
         if name in legs:
             run_leg(name, fn)
     result["tuned"] = tuned
-    if not args.no_cpu:
-        run_leg("cpu_baseline", leg_cpu)
     print(json.dumps(result), flush=True)
 
 
