@@ -64,8 +64,9 @@ def test_hand_orbit_points(sysm, fp):
 
 @pytest.mark.parametrize("fp", ["f32", "f64"])
 def test_ragged_tiles_and_edges(sysm, fp):
-    """Widths and row counts that are not multiples of the 4x16 pixel block
-    or of the work tile, tiles starting at odd rows, and an empty tile."""
+    """Widths and row counts that are not multiples of the 4x16 pixel block,
+    of a wave's block group (8x32 pixels in float, 8x16 in double) or of the
+    work tile, tiles starting at odd rows, and an empty tile."""
     from paper_1505_07368_amd import binding as cg
     code = cg.F32 if fp == "f32" else cg.F64
     vp = gen.boundary_viewport(5, width=203, height=77, max_iter=400)
