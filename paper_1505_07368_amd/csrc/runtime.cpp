@@ -580,6 +580,8 @@ int check_signature(const ActorRec& a, const void* args, uint64_t args_bytes, co
       if (m->fp != CAF_F32 && m->fp != CAF_F64) return CAF_E_INVALID;
       if ((uint64_t)m->row0 + m->rows > m->height) return CAF_E_INVALID;
       if (m->width > (1u << 20) || m->rows > (1u << 20)) return CAF_E_INVALID;
+      // at most 2^32 pixels (an 8 GiB reply), so block and tile counts fit 32 bits
+      if ((uint64_t)m->rows * m->width > (1ull << 32)) return CAF_E_INVALID;
       *out = Shape{a.spawn.palette_len ? CAF_U32 : CAF_U16, (uint64_t)m->rows * m->width, m->rows,
                    m->width};
       return CAF_OK;

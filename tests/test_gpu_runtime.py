@@ -562,6 +562,9 @@ def test_degenerate_and_maximum_arguments(sysm):
     assert sysm.request_raw(m, cg.mandel_args(vp, max_iter=65536))[0] == cg.E_INVALID
     assert sysm.request_raw(m, cg.mandel_args(Viewport(0, 0, 1, 1, 0, 1, 10)))[0] == cg.E_INVALID
     assert sysm.request_raw(m, cg.mandel_args(vp, fp=cg.I32))[0] == cg.E_INVALID
+    # more than 2^32 pixels (each side within its own limit of 2^20)
+    huge = Viewport(0, 0, 1e-6, 1e-6, 1 << 20, 1 << 13, 10)
+    assert sysm.request_raw(m, cg.mandel_args(huge))[0] == cg.E_INVALID
     e = sysm.spawn(cg.BHV_NOOP)
     assert sysm.request_raw(e, None, [np.zeros(0, np.int32)])[0] == cg.E_INVALID
     # max_iter = 65535 at c = 0 (never escapes) and 1 at c = 3 (escapes at once)
