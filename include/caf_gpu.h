@@ -153,8 +153,9 @@ typedef struct {
 typedef struct {
   double re_min, im_min;   /* lower-left corner of the whole image */
   double step_re, step_im; /* pixel pitch; pixel (x, y) samples re_min + x*step_re + i*(im_min + (row0+y)*step_im) */
-  uint32_t width, height;  /* whole image size */
-  uint32_t row0, rows;     /* this tile: global rows [row0, row0 + rows) */
+  uint32_t width, height;  /* whole image size; width 1 .. 2^20 */
+  uint32_t row0, rows;     /* this tile: global rows [row0, row0 + rows), rows <= 2^20,
+                              rows * width <= 2^32 (else CAF_E_INVALID) */
   uint32_t max_iter;       /* 1 .. 65535 */
   int32_t fp;              /* CAF_F32 (viewport doubles rounded to float once) or CAF_F64 */
 } caf_mandel_args;
