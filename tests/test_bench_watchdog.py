@@ -1,6 +1,6 @@
-"""The bench's leg watchdog (host logic, no GPU): a leg that stops making
+"""bench.py host logic (no GPU): the leg watchdog (a leg that stops making
 progress ends the run with one JSON line that keeps the results so far and
-marks the stalled leg."""
+marks the stalled leg) and the one-GPU check."""
 import json
 import os
 import subprocess
@@ -36,3 +36,12 @@ def test_stalled_leg_ends_the_run_with_one_json_line():
     assert "no progress" in out["serving"]["error"]
     assert out["tuned"] == {"mandel": {"grid": 0}}
     assert "no progress" in p.stderr
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """bench.py measures one GPU: any other --gpus value exits at once with a
+    message (before touching a device)."""
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
