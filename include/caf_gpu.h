@@ -100,7 +100,8 @@ typedef enum {
 /* Order in which a drained batch's work is laid out for the workgroups. */
 typedef enum {
   CAF_GROUP_FIFO = 0, /* mailbox order */
-  CAF_GROUP_LPT = 1   /* grouped by behaviour, largest GEMMs first (stable) */
+  CAF_GROUP_LPT = 1,  /* grouped by behaviour, largest GEMMs first (stable) */
+  CAF_GROUP_KIND = 2  /* grouped by behaviour, mailbox order within a group (stable) */
 } caf_grouping;
 
 typedef uint64_t caf_actor; /* actor address (Sec. 4.5 actor_addr); 0 is never valid */

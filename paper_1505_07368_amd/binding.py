@@ -21,7 +21,10 @@ OK, E_INVALID, E_NO_ACTOR, E_OVERLOAD, E_TIMEOUT, E_DEVICE, E_QUIT, E_FAULT = (
 I32, U16, F32, F64, BF16, U64, U32 = 0, 1, 2, 3, 4, 5, 6
 BHV_NOOP, BHV_MANDELBROT, BHV_GEMM, BHV_TANH, BHV_ROWSUM, BHV_HASHCHAIN, BHV_FAULT = range(7)
 MODE_PLAIN, MODE_BATCHED, MODE_PERSISTENT, MODE_PLAIN_GRAPH = 0, 1, 2, 3
-GROUP_FIFO, GROUP_LPT = 0, 1
+GROUP_FIFO, GROUP_LPT, GROUP_KIND = 0, 1, 2
+# drained batch layout: mailbox order, by behaviour with the largest GEMMs
+# first, or by behaviour in mailbox order (the default)
+GROUPINGS = {"fifo": GROUP_FIFO, "lpt": GROUP_LPT, "kind": GROUP_KIND}
 MODES = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "persistent": MODE_PERSISTENT,
          "plain_graph": MODE_PLAIN_GRAPH}
 
@@ -240,7 +243,7 @@ class System:
     """A compute-actor system on one GPU with a torch-allocated arena."""
 
     def __init__(self, mode="persistent", arena_bytes=1 << 30, device=0, ring_slots=4096,
-                 max_batch=1024, grid=0, blocking=True, idle_exit_us=0, grouping="lpt",
+                 max_batch=1024, grid=0, blocking=True, idle_exit_us=0, grouping="kind",
                  mandel_tile_px=0, gemm_tile=0, gemm_tile_class=(0, 0, 0, 0), full_wgs_per_cu=0):
         torch = _torch()
         self.L = load()
@@ -254,7 +257,7 @@ class System:
             device, self.mode, C.c_void_p(self.stream.cuda_stream),
             C.c_void_p(self.dstream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
             arena_bytes, ring_slots, max_batch, grid, 1 if blocking else 0, idle_exit_us,
-            GROUP_LPT if grouping == "lpt" else GROUP_FIFO, mandel_tile_px, gemm_tile,
+            GROUPINGS[grouping], mandel_tile_px, gemm_tile,
             (C.c_uint32 * 4)(*gemm_tile_class), full_wgs_per_cu)
         torch.cuda.synchronize(device)
         h = C.c_void_p()

@@ -501,9 +501,16 @@ plain_kernel(KArgs, Desc d, uint32_t ntiles) {
 
 // ---- the mailbox drain ----------------------------------------------------
 
-__device__ __forceinline__ uint32_t group_key(const Desc& e) {
+// Sort key of a drained entry (smaller keys are laid out first): the
+// behaviour, and under CAF_GROUP_LPT the product size too, largest first.
+// CAF_GROUP_KIND groups by behaviour only and keeps the mailbox order of the
+// products: sorting a pass largest first leaves its end to the smallest
+// products, whose fixed per-product costs weigh most, while the next pass
+// starts with large ones again.
+__device__ __forceinline__ uint32_t group_key(const Desc& e, uint32_t grouping) {
   switch (e.behavior) {
     case CAF_BHV_GEMM: {
+      if (grouping != CAF_GROUP_LPT) return 0u;
       const uint32_t n = e.p.g.n;
       return n >= 512 ? 0u : n >= 256 ? 1u : n >= 128 ? 2u : n >= 64 ? 3u : 4u;
     }
@@ -772,7 +779,7 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
     L.nt[i] = alive ? desc_ntiles(e) : 0u;
     L.dead[i] = alive ? 0 : 1;
     if (!alive) L.any_dead = 1;
-    L.key[i] = (uint8_t)(a.grouping == CAF_GROUP_LPT ? group_key(e) : 0u);
+    L.key[i] = (uint8_t)(a.grouping != CAF_GROUP_FIFO ? group_key(e, a.grouping) : 0u);
     const bool hash_here = alive && e.behavior == CAF_BHV_HASHCHAIN && e.hop_actor[0] == 0 &&
                            (e.flags & (DF_INLINE_OUT | DF_SEND)) != 0;
     L.hactor[i] = hash_here ? (uint16_t)(e.actor + 1u) : (uint16_t)0;
@@ -860,7 +867,7 @@ __device__ __forceinline__ bool drain_once_body(KArgsC& a, DrainLds& L, bool may
     if (t < 64) run_hash_entries_locked(a, L, cnt);
     __syncthreads();
     // Grouping: stable counting sort of the batch by key.
-    if (a.grouping == CAF_GROUP_LPT) {
+    if (a.grouping != CAF_GROUP_FIFO) {
       for (uint32_t i = t; i < cnt; i += kThreads) atomicAdd(&L.hist[L.key[i]], 1u);
       __syncthreads();
       if (t == 0) {

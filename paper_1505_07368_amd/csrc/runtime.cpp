@@ -1067,7 +1067,9 @@ int caf_gpu_init(const caf_gpu_config* cfg, caf_gpu_system** out) {
   if (!tile_ok(cfg->gemm_tile)) return CAF_E_INVALID;
   for (uint32_t t : cfg->gemm_tile_class)
     if (!tile_ok(t)) return CAF_E_INVALID;
-  if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT) return CAF_E_INVALID;
+  if (cfg->grouping != CAF_GROUP_FIFO && cfg->grouping != CAF_GROUP_LPT &&
+      cfg->grouping != CAF_GROUP_KIND)
+    return CAF_E_INVALID;
   if (cfg->full_wgs_per_cu != 0 && cfg->full_wgs_per_cu != 2 && cfg->full_wgs_per_cu != 3)
     return CAF_E_INVALID;
   if (hipSetDevice(cfg->device) != hipSuccess) return CAF_E_DEVICE;

@@ -74,3 +74,27 @@ def test_struct_layouts_match_header(tmp_path):
         ct = structs[name]
         got = C.sizeof(ct) if field == "size" else getattr(ct, field).offset
         assert got == int(val), (name, field, got, val)
+
+
+def test_enum_values_match_header(tmp_path):
+    """The binding's behaviour, mode and grouping constants equal the header's
+    enumerators (compiled by gcc)."""
+    import subprocess
+    pairs = {"CAF_BHV_NOOP": cg.BHV_NOOP, "CAF_BHV_MANDELBROT": cg.BHV_MANDELBROT,
+             "CAF_BHV_GEMM": cg.BHV_GEMM, "CAF_BHV_TANH": cg.BHV_TANH,
+             "CAF_BHV_ROWSUM": cg.BHV_ROWSUM, "CAF_BHV_HASHCHAIN": cg.BHV_HASHCHAIN,
+             "CAF_BHV_FAULT": cg.BHV_FAULT, "CAF_MODE_PLAIN": cg.MODE_PLAIN,
+             "CAF_MODE_BATCHED": cg.MODE_BATCHED, "CAF_MODE_PERSISTENT": cg.MODE_PERSISTENT,
+             "CAF_MODE_PLAIN_GRAPH": cg.MODE_PLAIN_GRAPH, "CAF_GROUP_FIFO": cg.GROUP_FIFO,
+             "CAF_GROUP_LPT": cg.GROUP_LPT, "CAF_GROUP_KIND": cg.GROUP_KIND}
+    lines = ['#include <stdio.h>', f'#include "{HEADER}"', 'int main(){']
+    lines += [f'printf("{k} %d\\n", (int){k});' for k in pairs]
+    lines.append("return 0;}")
+    src = tmp_path / "enums.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "enums"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict((k, int(v)) for k, v in (l.split() for l in out.splitlines()))
+    assert got == pairs
+    assert set(cg.GROUPINGS.values()) == {cg.GROUP_FIFO, cg.GROUP_LPT, cg.GROUP_KIND}

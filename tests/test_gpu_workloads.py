@@ -159,20 +159,20 @@ def test_gemm_batch_sampled(dtype, te, wgs):
     assert seen == {64, 128, 256, 512}
 
 
-@pytest.mark.parametrize("wgs", [2, 3])
-def test_serving_mix_full(wgs):
+@pytest.mark.parametrize("wgs, grouping", [(2, "kind"), (3, "kind"), (2, "lpt"), (3, "fifo")])
+def test_serving_mix_full(wgs, grouping):
     """Every request of a 0.1 s serving-mix run at 1e4 arrivals/s (about
     1,000 messages, issued as one burst through the same system
-    configuration as the serving benchmark, with either full drain variant):
-    every Mandelbrot square compared pixel for pixel, every GEMM in full
-    (relative Frobenius error)."""
+    configuration as the serving benchmark, with either full drain variant
+    and each layout of a drained batch): every Mandelbrot square compared
+    pixel for pixel, every GEMM in full (relative Frobenius error)."""
     import torch
     from paper_1505_07368_amd import binding as cg
     d = gen.serving_mix_arrays(0, 1e4, 0.1)
     cnt = d["arrival_ns"].size
     assert cnt >= 900
     s = cg.System(mode="persistent", arena_bytes=32 << 30, ring_slots=8192, blocking=False,
-                  full_wgs_per_cu=wgs)
+                  full_wgs_per_cu=wgs, grouping=grouping)
     try:
         m = s.spawn(cg.BHV_MANDELBROT)
         gm = s.spawn(cg.BHV_GEMM)
