@@ -681,10 +681,11 @@ void fill_desc(const caf_gpu_system* s, const ActorRec& a, uint32_t aidx, const 
       if (g->in_dtype == CAF_BF16) d->flags |= DF_BF16;
       d->p.g.n = g->n;
       d->tcfg = gemm_tile_for(s, g, in);
-      // 128 x 256 tiles: units of two, one 128-row block of an n = 512
-      // product (its A panel shared); measured against 4 (2.5% slower) and
-      // 8 (10-25% slower: too coarse to end a batch evenly)
-      d->p.g.unit = g->in_dtype != CAF_BF16 ? 1u : d->tcfg == 256 ? 2u : kGemmUnitBf16;
+      // bf16 products in units of four tiles, 128 x 256 ones too (half of an
+      // n = 512 product; with drained products in mailbox order four ran a
+      // batch 1.5-3% faster than two and 7% faster than eight, whose units
+      // are too coarse to end a batch evenly); fp32 in single tiles
+      d->p.g.unit = g->in_dtype != CAF_BF16 ? 1u : kGemmUnitBf16;
       break;
     }
     case CAF_BHV_TANH:
