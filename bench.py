@@ -821,17 +821,20 @@ def main():
                      ("small", leg_small)):
         if name in legs:
             run_leg(name, fn)
+    # the CPU baseline and the offload leg before serving, the longest and
+    # most loaded leg: if a leg stalls, the watchdog's line still has them.
+    # The GEMM batches, bound by memory traffic, run late: right after a
+    # heavy run (a test suite) their first minutes have been slower.
+    if not args.no_cpu:
+        run_leg("cpu_baseline", leg_cpu)
+    for name, fn in (("pipeline", leg_pipeline), ("offload", leg_offload)):
+        if name in legs:
+            run_leg(name, fn)
     if "gemm" in legs:
         for dt in args.gemm_dtypes.split(","):
             run_leg(f"gemm_{dt}", lambda dt=dt: leg_gemm(dt))
-    # the CPU baseline and the offload leg before serving, the longest and
-    # most loaded leg: if a leg stalls, the watchdog's line still has them
-    if not args.no_cpu:
-        run_leg("cpu_baseline", leg_cpu)
-    for name, fn in (("pipeline", leg_pipeline), ("offload", leg_offload),
-                     ("serving", leg_serving)):
-        if name in legs:
-            run_leg(name, fn)
+    if "serving" in legs:
+        run_leg("serving", leg_serving)
     result["tuned"] = tuned
     print(json.dumps(result), flush=True)
 
